@@ -1,0 +1,171 @@
+/*
+ * cpmttkrp -- dense MTTKRP, CP-ALS sweep and CP least-squares gradient on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Operations follow Hayashi, Ballard, Jiang, Tobia, "Shared-Memory
+ * Parallelization of MTTKRP for Dense Tensors" (2018):
+ *
+ *   MTTKRP (Section 2.2, first of the three CP-ALS operations):
+ *     M = X_(n) (U_{N-1} kr ... kr U_{n+1} kr U_{n-1} kr ... kr U_0),
+ *     i.e. M(i_n, c) = sum over the entries with mode-n index i_n of
+ *          X(i_0..i_{N-1}) * prod_{k != n} U_k(i_k, c).
+ *   CP-ALS factor update (Section 2.2): M as above, H = Hadamard product of
+ *     the Grams U_k^T U_k over k != n, U_n = M H^-1.
+ *   CP gradient (Section 2.2 notes MTTKRP is part of the gradient): for
+ *     f = 1/2 ||X - [[U_0..U_{N-1}]]||_F^2, df/dU_n = U_n H_n - MTTKRP_n.
+ *
+ * Layout conventions shared by every entry point
+ *   - dims[0..N-1] are I_0..I_{N-1}; X is stored in the natural
+ *     linearisation of Section 2.1, l = sum_n i_n prod_{k<n} I_k, so mode 0
+ *     is the stride-1 index.  (A C-contiguous array of shape
+ *     (I_{N-1}, ..., I_0) has exactly this layout.)  The tensor is never
+ *     permuted or copied.
+ *   - factors[k] is an I_k x R matrix, row-major (R contiguous).
+ *   - MTTKRP outputs and gradients are I_n x R, row-major, fully overwritten.
+ *   - Element types by cpm_dtype:
+ *       CPM_F32    : X float32, factors/outputs float32.
+ *       CPM_F64    : X float64, factors/outputs float64.
+ *       CPM_BF16X2 : X is 2*I bfloat16 values (uint16 bit patterns): the hi
+ *                    plane (I values) followed by the lo plane; an entry's
+ *                    value is hi + lo.  Factors/outputs float32.  The
+ *                    contraction runs on bf16 MFMA with float32 accumulation
+ *                    using hi*hi + hi*lo + lo*hi products of the split tensor
+ *                    and of the split Khatri-Rao rows.
+ *
+ * Ownership: every pointer named "device" is caller-owned device memory on
+ * the current HIP device; pointer arrays (factors, grads) and dims are host
+ * memory read during the call only.  The library allocates no memory and
+ * keeps no state between calls apart from the thread-local error message.
+ * Workspaces are caller-provided; query their size with the *_workspace_bytes
+ * functions (0 is a valid size; a null workspace is then accepted).
+ *
+ * Errors: every call returns a cpm_status.  All argument validation happens
+ * before any HIP call, so invalid arguments never launch work.  A HIP
+ * runtime failure returns CPM_EHIP.  cpm_last_error() gives a message for
+ * the last non-OK status returned on the calling thread.
+ *
+ * Ordering: work is enqueued on `stream` and calls return without waiting,
+ * except cp_als_step, which waits once for the stream to learn whether every
+ * Cholesky factorisation succeeded (and to return the fit when asked).
+ *
+ * Limits: 1 <= N <= 12, every dim >= 1, prod(dims) < 2^62, 1 <= R <= 256
+ * (R <= 128 for cp_als_step and cp_grad).
+ */
+#ifndef CPMTTKRP_H
+#define CPMTTKRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CPM_OK = 0,
+    CPM_EINVAL = 1,       /* bad argument: null pointer, bad dims/mode/R */
+    CPM_EUNSUPPORTED = 2, /* valid but outside the library's limits */
+    CPM_ENOTPD = 3,       /* cp_als_step: Hadamard-of-Grams not positive definite */
+    CPM_EHIP = 4,         /* HIP runtime error (launch or synchronisation) */
+    CPM_EWORKSPACE = 5    /* workspace null or smaller than the queried size */
+} cpm_status;
+
+typedef enum { CPM_F32 = 0, CPM_F64 = 1, CPM_BF16X2 = 2 } cpm_dtype;
+
+#define CPM_MAX_MODES 12
+#define CPM_MAX_RANK 256
+#define CPM_MAX_RANK_SOLVE 128
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int cpm_version(void);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *cpm_last_error(void);
+
+/*
+ * Bytes of workspace `mttkrp` needs for this shape, mode, rank and type.
+ * Returns 0 for invalid arguments too (the call itself then reports them).
+ */
+size_t cpm_mttkrp_workspace_bytes(const int64_t *dims, int N, int R, int mode, cpm_dtype dt);
+
+/*
+ * Mode-`mode` MTTKRP (Section 2.2).  X: device tensor; factors: host array
+ * of N device pointers (factors[mode] is not read and may be null); out:
+ * device I_mode x R.  Internal modes fuse the partial MTTKRP against the
+ * left Khatri-Rao product with the multi-TTV against the right one (the
+ * 2-step scheme of Section 4.3); Khatri-Rao rows are formed on the fly
+ * (the row-wise product with reuse of Section 4.1) and never stored.
+ * The result is bitwise reproducible run to run.
+ */
+cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                  int mode, void *out, cpm_dtype dt, void *workspace, size_t ws_bytes,
+                  hipStream_t stream);
+
+/* Bytes of workspace for cp_als_step / cp_grad. */
+size_t cpm_cp_als_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);
+size_t cpm_cp_grad_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);
+
+/*
+ * One CP-ALS sweep (Section 2.2): for n = 0..N-1 in order, M = MTTKRP_n with
+ * the current factors, H = Hadamard product of the other Grams (float64),
+ * Cholesky H = L L^T (float64), U_n = M H^-1 (float64, stored in the
+ * factor type).  factors: host array of N device pointers, updated in
+ * place.  If any H is not positive definite, every factor is restored to
+ * its input value and CPM_ENOTPD is returned.  xnorm2: ||X||_F^2 if known,
+ * or negative to have it computed (only needed when fit_out is non-null).
+ * fit_out: host pointer, may be null; receives 1 - ||X - Y|| / ||X|| of the
+ * updated model (from ||X||^2 - 2 <M_{N-1}, U_{N-1}> + sum(Hadamard of all
+ * Grams), accumulated in float64).  Waits for the stream once.
+ * R <= 128.
+ */
+cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *factors, int R,
+                       cpm_dtype dt, double xnorm2, double *fit_out, void *workspace,
+                       size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Gradient of f = 1/2 ||X - [[U_0..U_{N-1}]]||_F^2 for every factor:
+ * grads[n] = U_n H_n - MTTKRP_n (device I_n x R each; grads may be null to
+ * compute only the loss, and single entries may be null to skip a mode).
+ * loss_dev: device double, may be null; receives f evaluated as
+ * 1/2 (||X||^2 - 2 <MTTKRP_{N-1}, U_{N-1}> + sum(Hadamard of all Grams)),
+ * accumulated in float64, the residual itself never being formed.
+ * xnorm2: ||X||_F^2 if known, negative to compute it on the device.
+ * R <= 128.
+ */
+cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                   void *const *grads, double xnorm2, double *loss_dev, cpm_dtype dt,
+                   void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * ||X||_F^2 accumulated in float64 into *out_dev (device double).
+ * Workspace: cpm_xnorm2_workspace_bytes().
+ */
+size_t cpm_xnorm2_workspace_bytes(const int64_t *dims, int N, cpm_dtype dt);
+cpm_status cpm_xnorm2(const void *X, const int64_t *dims, int N, cpm_dtype dt, double *out_dev,
+                      void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Split `count` float32 values into bfloat16 planes: hi = RNE(x) and
+ * lo = RNE(x - hi) (x - hi is exact in float32).  planes: device, 2*count
+ * uint16 values, hi plane first -- the CPM_BF16X2 tensor format.
+ */
+cpm_status cpm_split_bf16(const float *x, int64_t count, uint16_t *planes, hipStream_t stream);
+
+/*
+ * Rows [j0, j0 + nrows) of the Khatri-Rao product mats[0] kr ... kr
+ * mats[Z-1] (Section 2.1: the last matrix's row index varies fastest),
+ * formed by the same on-the-fly row builder the MTTKRP kernels use.
+ * mats: host array of Z device pointers to J_z x R row-major matrices
+ * (float32 for CPM_F32, float64 for CPM_F64); out: device nrows x R.
+ * 1 <= Z <= 12.
+ */
+cpm_status cpm_krp_rows(const void *const *mats, const int64_t *J, int Z, int R, int64_t j0,
+                        int64_t nrows, void *out, cpm_dtype dt, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPMTTKRP_H */

@@ -1,0 +1,265 @@
+// Kernels around MTTKRP for the CP-ALS update and the CP gradient
+// (Section 2.2): float64 Gram matrices and their Hadamard product, a
+// one-work-group Cholesky factorisation, row-parallel triangular solves,
+// the gradient U_n H_n - M_n, the loss scalars, ||X||^2, the bf16 split of
+// a float32 tensor and explicit Khatri-Rao rows.  Every reduction here runs
+// in a fixed order, so results are reproducible run to run.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace cpm {
+
+// Sets *flag = 0 (a kernel rather than a memset so the sequence can be
+// captured into a graph).
+__global__ void k_clear_status(int *flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
+}
+
+__global__ void k_set_scalar(double *dst, double v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+
+// Partial Grams over row blocks: part[b][a][c] = sum_{i in block b} U[i][a] U[i][c].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gram_partial(const T *__restrict__ U, int64_t I, int R,
+                                                           int64_t rows_per_block, double *__restrict__ part) {
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t i1 = min(I, i0 + rows_per_block);
+    double *dst = part + (int64_t)blockIdx.x * R * R;
+    for (int e = threadIdx.x; e < R * R; e += kThreads) {
+        const int a = e / R, c = e % R;
+        double s = 0.0;
+        for (int64_t i = i0; i < i1; ++i) s += (double)U[i * R + a] * (double)U[i * R + c];
+        dst[e] = s;
+    }
+}
+
+// out[e] = sum_{b < nslices} part[b][e], in slice order.
+__global__ __launch_bounds__(kThreads) void k_sum_slices(const double *__restrict__ part, int64_t nslices,
+                                                         int64_t count, double *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int64_t b = 0; b < nslices; ++b) s += part[b * count + e];
+    out[e] = s;
+}
+
+// H = Hadamard product of grams[k] (R x R each) over k != skip.
+__global__ __launch_bounds__(kThreads) void k_hadamard_except(const double *__restrict__ grams, int N, int R,
+                                                              int skip, double *__restrict__ H) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= R * R) return;
+    double v = 1.0;
+    for (int k = 0; k < N; ++k)
+        if (k != skip) v *= grams[(int64_t)k * R * R + e];
+    H[e] = v;
+}
+
+// Cholesky H = L L^T of an R x R float64 matrix held in LDS by one work-group
+// (right-looking: scale the pivot column, update the trailing block).
+// Writes L (row-major, zero above the diagonal) and its transpose Lt.  If a
+// pivot is not positive the factorisation stops and *status is set to 1
+// (it is never cleared here, so one failure in a sweep is remembered).
+__global__ __launch_bounds__(kThreads) void k_cholesky(const double *__restrict__ H, int R,
+                                                       double *__restrict__ L, double *__restrict__ Lt,
+                                                       int *__restrict__ status) {
+    extern __shared__ double A[];  // R x R
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    for (int e = t; e < R * R; e += kThreads) A[e] = H[e];
+    if (t == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < R; ++j) {
+        const double d = A[j * R + j];
+        if (!(d > 0.0)) {
+            if (t == 0) bad = 1;
+            break;  // d is the same value in every thread: uniform exit
+        }
+        const double ljj = sqrt(d);
+        __syncthreads();
+        for (int i = j + 1 + t; i < R; i += kThreads) A[i * R + j] /= ljj;
+        if (t == 0) A[j * R + j] = ljj;
+        __syncthreads();
+        const int w = R - j - 1;  // trailing block size
+        for (int e = t; e < w * w; e += kThreads) {
+            const int i = j + 1 + e / w, k = j + 1 + e % w;
+            if (k <= i) A[i * R + k] -= A[i * R + j] * A[k * R + j];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (t == 0) *status = 1;
+        return;
+    }
+    for (int e = t; e < R * R; e += kThreads) {
+        const int i = e / R, k = e % R;
+        const double v = (k <= i) ? A[e] : 0.0;
+        L[e] = v;
+        Lt[k * R + i] = v;
+    }
+}
+
+// Row-parallel solve x H = m for every row of M (H = L L^T): L y = m^T then
+// L^T x^T = y.  One wave per row; lane k holds entries k and k + 64 (R <= 128).
+// Skipped entirely when *status is set, leaving out untouched.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_chol_solve_rows(const double *__restrict__ L,
+                                                              const double *__restrict__ Lt,
+                                                              const int *__restrict__ status,
+                                                              const T *__restrict__ M, int64_t In, int R,
+                                                              T *__restrict__ out) {
+    if (*status) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+    if (row >= In) return;
+    const int k0 = lane, k1 = lane + 64;
+    double v0 = (k0 < R) ? (double)M[row * R + k0] : 0.0;
+    double v1 = (k1 < R) ? (double)M[row * R + k1] : 0.0;
+    for (int j = 0; j < R; ++j) {  // forward: column j of L is row j of Lt
+        const double src = (j < 64) ? v0 : v1;
+        const double yj = __shfl(src, j & 63) / L[j * R + j];
+        if (j < 64) { if (lane == j) v0 = yj; } else { if (lane == j - 64) v1 = yj; }
+        const double *col = Lt + (int64_t)j * R;
+        if (k0 > j && k0 < R) v0 -= col[k0] * yj;
+        if (k1 > j && k1 < R) v1 -= col[k1] * yj;
+    }
+    for (int j = R - 1; j >= 0; --j) {  // backward: column j of L^T is row j of L
+        const double src = (j < 64) ? v0 : v1;
+        const double xj = __shfl(src, j & 63) / L[j * R + j];
+        if (j < 64) { if (lane == j) v0 = xj; } else { if (lane == j - 64) v1 = xj; }
+        const double *rowL = L + (int64_t)j * R;
+        if (k0 < j) v0 -= rowL[k0] * xj;
+        if (k1 < j && k1 < R) v1 -= rowL[k1] * xj;
+    }
+    if (k0 < R) out[row * R + k0] = (T)v0;
+    if (k1 < R) out[row * R + k1] = (T)v1;
+}
+
+// Restore every factor from its snapshot when *status is set.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restore_if_failed(const int *__restrict__ status,
+                                                                const T *__restrict__ snap, int64_t count,
+                                                                T *__restrict__ dst) {
+    if (!*status) return;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < count; e += (int64_t)gridDim.x * kThreads)
+        dst[e] = snap[e];
+}
+
+// grad[i][c] = sum_d U[i][d] H[d][c] - M[i][c], in float64.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_grad(const T *__restrict__ U, const double *__restrict__ H,
+                                                   const T *__restrict__ M, int64_t In, int R,
+                                                   T *__restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= In * R) return;
+    const int64_t i = e / R;
+    const int c = (int)(e % R);
+    double s = 0.0;
+    for (int d = 0; d < R; ++d) s += (double)U[i * R + d] * H[d * R + c];
+    G[e] = (T)(s - (double)M[e]);
+}
+
+// Fixed-order block sum of 256 per-thread doubles; valid in thread 0.
+__device__ inline double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// *out = sum_e a[e] * b[e] in float64 (one work-group).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot(const T *__restrict__ a, const T *__restrict__ b, int64_t n,
+                                                  double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < n; e += kThreads) s += (double)a[e] * (double)b[e];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// f = 1/2 (||X||^2 - 2 <M_{N-1}, U_{N-1}> + sum_ab prod_k G_k[a][b]); with
+// want_fit the result is 1 - sqrt(max(0, 2 f)) / sqrt(||X||^2) instead.
+__global__ __launch_bounds__(kThreads) void k_loss(const double *__restrict__ xnorm2,
+                                                   const double *__restrict__ inner,
+                                                   const double *__restrict__ grams, int N, int R,
+                                                   int want_fit, double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < R * R; e += kThreads) {
+        double v = 1.0;
+        for (int k = 0; k < N; ++k) v *= grams[(int64_t)k * R * R + e];
+        s += v;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        const double f = 0.5 * (*xnorm2 - 2.0 * *inner + s);
+        *out = want_fit ? 1.0 - sqrt(fmax(0.0, 2.0 * f)) / sqrt(*xnorm2) : f;
+    }
+}
+
+// Per-block partial sums of squares of the tensor entries (bf16 pairs are
+// widened to hi + lo, which is exact in float32).
+template <int DT>
+__global__ __launch_bounds__(kThreads) void k_sumsq_partial(const void *__restrict__ Xv, int64_t I,
+                                                            double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < I; e += stride) {
+        double x;
+        if (DT == CPM_F32) {
+            x = (double)((const float *)Xv)[e];
+        } else if (DT == CPM_F64) {
+            x = ((const double *)Xv)[e];
+        } else {
+            const uint16_t *p = (const uint16_t *)Xv;
+            x = (double)(bf16_bits_to_float(p[e]) + bf16_bits_to_float(p[I + e]));
+        }
+        s += x * x;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum_vector(const double *__restrict__ part, int n,
+                                                         double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < n; e += kThreads) s += part[e];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// hi = RNE(x), lo = RNE(x - hi): the bf16 pair format.
+__global__ __launch_bounds__(kThreads) void k_split_bf16(const float *__restrict__ x, int64_t n,
+                                                         uint16_t *__restrict__ planes) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+        const float v = x[e];
+        const uint16_t h = bf16_rne_bits(v);
+        const uint16_t l = bf16_rne_bits(v - bf16_bits_to_float(h));
+        planes[e] = h;
+        planes[n + e] = l;
+    }
+}
+
+// Explicit rows [j0, j0 + nrows) of a Khatri-Rao product, built by the same
+// row builder the MTTKRP kernels use; 64 rows per block.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_krp_rows(Krp<T> k, int R, int RP, int64_t j0, int64_t nrows,
+                                                       T *__restrict__ out) {
+    const int64_t q0 = (int64_t)blockIdx.x * 64;
+    const int cnt = (int)min((int64_t)64, nrows - q0);
+    build_krp_rows<T>(k, R, 0, RP, j0 + q0, cnt, j0 + nrows, [&](int q, int c, T v) {
+        if (c < R) out[(q0 + q) * R + c] = v;
+    });
+}
+
+}  // namespace cpm

@@ -1,0 +1,741 @@
+// C-ABI of the cpmttkrp library: argument validation, launch planning and
+// the entry points declared in include/cpmttkrp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/cpmttkrp.h"
+#include "als_kernels.hpp"
+#include "mttkrp_kernels.hpp"
+
+using namespace cpm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cpm_status fail(cpm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(CPM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+#define LAUNCH_CHECK(what)                                                             \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess) return fail(CPM_EHIP, "launch of %s failed: %s", what,   \
+                                          hipGetErrorString(e_));                      \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t dtype_x_bytes(cpm_dtype dt) { return dt == CPM_F64 ? 8 : (dt == CPM_F32 ? 4 : 4); }
+size_t dtype_f_bytes(cpm_dtype dt) { return dt == CPM_F64 ? 8 : 4; }
+
+// Shape checks shared by every tensor entry point.  Touches host memory only.
+cpm_status check_shape(const int64_t *dims, int N, int R, int64_t *total, int Rmax) {
+    if (!dims) return fail(CPM_EINVAL, "dims is null");
+    if (N < 1 || N > CPM_MAX_MODES) return fail(CPM_EINVAL, "N=%d outside [1, %d]", N, CPM_MAX_MODES);
+    if (R < 1) return fail(CPM_EINVAL, "R=%d < 1", R);
+    if (R > Rmax) return fail(CPM_EUNSUPPORTED, "R=%d above the limit %d", R, Rmax);
+    int64_t t = 1;
+    for (int k = 0; k < N; ++k) {
+        if (dims[k] < 1) return fail(CPM_EINVAL, "dims[%d]=%lld < 1", k, (long long)dims[k]);
+        if (t > ((int64_t)1 << 62) / dims[k]) return fail(CPM_EUNSUPPORTED, "tensor has 2^62 or more entries");
+        t *= dims[k];
+    }
+    *total = t;
+    return CPM_OK;
+}
+
+cpm_status check_dtype(cpm_dtype dt) {
+    if (dt != CPM_F32 && dt != CPM_F64 && dt != CPM_BF16X2) return fail(CPM_EINVAL, "unknown dtype %d", (int)dt);
+    return CPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch planning for one mode.
+// ---------------------------------------------------------------------------
+enum Kind { kLeft = 0, kRight = 1, kBf16Left = 2, kBf16Right = 3 };
+
+struct Plan {
+    Kind kind;
+    int64_t IL, In, IR, J;
+    int NB, MB, WI, ncb;      // n-blocks per column block, m-blocks, wave rows, column blocks
+    int LC;                   // left: l-chunk; right: r-chunk rows
+    int64_t nlc, ups, units;  // left: chunks per slab, units per split, units per row tile
+    int64_t S, ntiles;        // splits, row tiles (left) / column tiles (right)
+    int64_t rps;              // right: rows per split
+    bool v4;
+    size_t lds;
+    bool reduce;              // partials need the reduction kernel
+    size_t partial_bytes;
+};
+
+constexpr int kTargetGroups = 1024;
+constexpr size_t kLdsBudget = 65536;
+
+int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const void *X) {
+    Plan p{};
+    p.IL = 1;
+    for (int k = 0; k < mode; ++k) p.IL *= dims[k];
+    p.In = dims[mode];
+    p.IR = 1;
+    for (int k = mode + 1; k < N; ++k) p.IR *= dims[k];
+    const size_t sz = dtype_f_bytes(dt);
+    const int RPtot = (R + 15) / 16 * 16;
+    const bool bf = dt == CPM_BF16X2;
+    if (bf) {
+        p.kind = kBf16Left;
+        return p;
+    }
+    const bool left = p.IL >= 16;
+    const int nbmax = (dt == CPM_F64) ? 4 : 8;
+    int nb = RPtot / 16;
+    if (nb <= nbmax) {
+        p.NB = pow2_at_least(nb);
+        p.ncb = 1;
+    } else {
+        p.NB = nbmax;
+        p.ncb = (int)ceil_div(nb, nbmax);
+    }
+    const int RP = p.NB * 16;
+    if (left) {
+        p.kind = kLeft;
+        const int budget_mb = (dt == CPM_F64) ? 8 : 16;
+        p.MB = std::min(4, std::max(1, budget_mb / p.NB));
+        while (p.MB > 1 && 16 * p.MB / 2 >= p.In) p.MB /= 2;
+        p.WI = 1;
+        const int pitch = RP + 4;
+        const int64_t il16 = ceil_div(p.IL, 16) * 16;
+        const size_t red = (size_t)4 * p.MB * p.NB * 256 * sz;
+        if ((size_t)il16 * pitch * sz <= kLdsBudget && il16 <= 1024) {
+            p.LC = (int)il16;
+            p.nlc = 1;
+        } else {
+            int lc = (int)(kLdsBudget / (2 * pitch * sz)) / 16 * 16;
+            lc = std::max(16, std::min(lc, 512));
+            p.LC = lc;
+            p.nlc = ceil_div(p.IL, lc);
+        }
+        const size_t tile = (size_t)(p.nlc == 1 ? 1 : 2) * p.LC * pitch * sz;
+        p.lds = std::max(tile, red);
+        p.ntiles = ceil_div(p.In, 16 * p.MB * p.WI);
+        p.units = p.IR * p.nlc;
+        int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.ncb));
+        S = std::min(S, p.units);
+        p.ups = ceil_div(p.units, S);
+        p.S = ceil_div(p.units, p.ups);
+        p.v4 = (p.IL % 4 == 0) && ((uintptr_t)X % (4 * sz) == 0);
+        p.J = p.In;
+        p.reduce = p.S > 1;
+        p.partial_bytes = p.reduce ? (size_t)p.S * p.In * R * sz : 0;
+    } else {
+        p.kind = kRight;
+        p.J = p.In * p.IL;
+        const int mjmax = (dt == CPM_F64) ? (p.NB <= 1 ? 2 : 1) : (p.NB <= 2 ? 2 : 1);
+        p.MB = (p.J <= 64) ? 1 : mjmax;  // MJ
+        p.WI = 4;
+        const int pitch = RP + 16;
+        int rc = (int)(kLdsBudget / (2 * pitch * sz)) / 16 * 16;
+        rc = std::max(16, std::min(rc, 256));
+        p.LC = rc;
+        const size_t red = (size_t)4096 * p.MB * p.NB * sz;
+        p.lds = std::max((size_t)2 * rc * pitch * sz, red);
+        p.ntiles = ceil_div(p.J, 64 * p.MB);
+        int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.ncb));
+        S = std::min(S, ceil_div(p.IR, 4));
+        p.rps = ceil_div(ceil_div(p.IR, S), 4) * 4;
+        p.S = ceil_div(p.IR, p.rps);
+        p.v4 = (p.J % 4 == 0) && ((uintptr_t)X % (4 * sz) == 0);
+        p.reduce = p.S > 1 || mode > 0;  // mode > 0: the multi-TTV with K_L runs in the reduction
+        p.partial_bytes = p.reduce ? (size_t)p.S * p.J * R * sz : 0;
+    }
+    return p;
+}
+
+template <typename T>
+Krp<T> make_krp(const void *const *factors, const int64_t *dims, int first, int last, bool &ok) {
+    // modes first..last-1, fastest first
+    Krp<T> k{};
+    k.Z = 0;
+    k.rows = 1;
+    ok = true;
+    for (int m = first; m < last; ++m) {
+        k.J[k.Z] = dims[m];
+        k.stride[k.Z] = k.rows;
+        k.U[k.Z] = reinterpret_cast<const T *>(factors[m]);
+        if (!factors[m]) ok = false;
+        k.rows *= dims[m];
+        ++k.Z;
+    }
+    return k;
+}
+
+// ----------------------------- kernel dispatch -----------------------------
+template <typename T, int NB, int MB, bool V4>
+void launch_left_t(const Plan &p, const T *X, const Krp<T> &kl, const Krp<T> &kr, int R, T *partial,
+                   hipStream_t st) {
+    dim3 grid((unsigned)p.ntiles, (unsigned)p.S, (unsigned)p.ncb);
+    hipLaunchKernelGGL((k_contract_left<T, NB, MB, V4>), grid, dim3(kThreads), p.lds, st, X, p.IL, p.In, p.IR,
+                       kl, kr, R, p.LC, p.WI, p.nlc, p.ups, p.units, partial);
+}
+
+template <typename T, int NB, int MB>
+void launch_left_v(const Plan &p, const T *X, const Krp<T> &kl, const Krp<T> &kr, int R, T *partial,
+                   hipStream_t st) {
+    if (p.v4) launch_left_t<T, NB, MB, true>(p, X, kl, kr, R, partial, st);
+    else launch_left_t<T, NB, MB, false>(p, X, kl, kr, R, partial, st);
+}
+
+template <typename T, int NB>
+void launch_left_m(const Plan &p, const T *X, const Krp<T> &kl, const Krp<T> &kr, int R, T *partial,
+                   hipStream_t st) {
+    switch (p.MB) {
+    case 1: launch_left_v<T, NB, 1>(p, X, kl, kr, R, partial, st); break;
+    case 2: launch_left_v<T, NB, 2>(p, X, kl, kr, R, partial, st); break;
+    default: launch_left_v<T, NB, 4>(p, X, kl, kr, R, partial, st); break;
+    }
+}
+
+template <typename T>
+void launch_left(const Plan &p, const T *X, const Krp<T> &kl, const Krp<T> &kr, int R, T *partial,
+                 hipStream_t st);
+template <>
+void launch_left<float>(const Plan &p, const float *X, const Krp<float> &kl, const Krp<float> &kr, int R,
+                        float *partial, hipStream_t st) {
+    switch (p.NB) {
+    case 1: launch_left_m<float, 1>(p, X, kl, kr, R, partial, st); break;
+    case 2: launch_left_m<float, 2>(p, X, kl, kr, R, partial, st); break;
+    case 4: launch_left_m<float, 4>(p, X, kl, kr, R, partial, st); break;
+    default: launch_left_m<float, 8>(p, X, kl, kr, R, partial, st); break;
+    }
+}
+template <>
+void launch_left<double>(const Plan &p, const double *X, const Krp<double> &kl, const Krp<double> &kr, int R,
+                         double *partial, hipStream_t st) {
+    switch (p.NB) {
+    case 1: launch_left_m<double, 1>(p, X, kl, kr, R, partial, st); break;
+    case 2: launch_left_m<double, 2>(p, X, kl, kr, R, partial, st); break;
+    default: launch_left_m<double, 4>(p, X, kl, kr, R, partial, st); break;
+    }
+}
+
+template <typename T, int NB, int MJ, bool V4>
+void launch_right_t(const Plan &p, const T *X, const Krp<T> &kr, int R, T *partial, hipStream_t st) {
+    dim3 grid((unsigned)p.ntiles, (unsigned)p.S, (unsigned)p.ncb);
+    hipLaunchKernelGGL((k_contract_right<T, NB, MJ, V4>), grid, dim3(kThreads), p.lds, st, X, p.J, p.IR, kr, R,
+                       p.LC, p.rps, partial);
+}
+
+template <typename T, int NB, int MJ>
+void launch_right_v(const Plan &p, const T *X, const Krp<T> &kr, int R, T *partial, hipStream_t st) {
+    if (p.v4) launch_right_t<T, NB, MJ, true>(p, X, kr, R, partial, st);
+    else launch_right_t<T, NB, MJ, false>(p, X, kr, R, partial, st);
+}
+
+template <typename T, int NB>
+void launch_right_m(const Plan &p, const T *X, const Krp<T> &kr, int R, T *partial, hipStream_t st) {
+    if (p.MB == 2) launch_right_v<T, NB, 2>(p, X, kr, R, partial, st);
+    else launch_right_v<T, NB, 1>(p, X, kr, R, partial, st);
+}
+
+template <typename T>
+void launch_right(const Plan &p, const T *X, const Krp<T> &kr, int R, T *partial, hipStream_t st);
+template <>
+void launch_right<float>(const Plan &p, const float *X, const Krp<float> &kr, int R, float *partial,
+                         hipStream_t st) {
+    switch (p.NB) {
+    case 1: launch_right_m<float, 1>(p, X, kr, R, partial, st); break;
+    case 2: launch_right_m<float, 2>(p, X, kr, R, partial, st); break;
+    case 4: launch_right_m<float, 4>(p, X, kr, R, partial, st); break;
+    default: launch_right_m<float, 8>(p, X, kr, R, partial, st); break;
+    }
+}
+template <>
+void launch_right<double>(const Plan &p, const double *X, const Krp<double> &kr, int R, double *partial,
+                          hipStream_t st) {
+    switch (p.NB) {
+    case 1: launch_right_m<double, 1>(p, X, kr, R, partial, st); break;
+    case 2: launch_right_m<double, 2>(p, X, kr, R, partial, st); break;
+    default: launch_right_m<double, 4>(p, X, kr, R, partial, st); break;
+    }
+}
+
+// Enqueue one MTTKRP (arguments already validated).
+template <typename T>
+cpm_status run_mttkrp_t(const Plan &p, const void *Xv, const int64_t *dims, int N, const void *const *factors,
+                        int R, int mode, void *outv, void *ws, hipStream_t st) {
+    bool ok1, ok2;
+    Krp<T> kl = make_krp<T>(factors, dims, 0, mode, ok1);
+    Krp<T> kr = make_krp<T>(factors, dims, mode + 1, N, ok2);
+    if (!ok1 || !ok2) return fail(CPM_EINVAL, "a factor pointer other than factors[mode] is null");
+    const T *X = reinterpret_cast<const T *>(Xv);
+    T *out = reinterpret_cast<T *>(outv);
+    T *partial = p.reduce ? reinterpret_cast<T *>(ws) : out;
+    if (p.kind == kLeft) {
+        launch_left<T>(p, X, kl, kr, R, partial, st);
+        LAUNCH_CHECK("k_contract_left");
+    } else {
+        launch_right<T>(p, X, kr, R, partial, st);
+        LAUNCH_CHECK("k_contract_right");
+    }
+    if (p.reduce) {
+        const int64_t total = p.In * R;
+        const int64_t rows_per_slice = (p.kind == kLeft) ? p.In : p.J;
+        const int64_t il = (p.kind == kLeft) ? 1 : p.IL;
+        Krp<T> kred = kl;
+        if (p.kind == kLeft) kred.Z = 0;  // K_L was applied inside the contraction
+        hipLaunchKernelGGL((k_reduce<T, T>), dim3((unsigned)ceil_div(total, 64)), dim3(kThreads), 0, st, partial,
+                           p.S, rows_per_slice, p.In, il, kred, R, out);
+        LAUNCH_CHECK("k_reduce");
+    }
+    return CPM_OK;
+}
+
+cpm_status run_mttkrp(const Plan &p, const void *X, const int64_t *dims, int N, const void *const *factors,
+                      int R, int mode, void *out, cpm_dtype dt, void *ws, hipStream_t st) {
+    if (dt == CPM_F32) return run_mttkrp_t<float>(p, X, dims, N, factors, R, mode, out, ws, st);
+    if (dt == CPM_F64) return run_mttkrp_t<double>(p, X, dims, N, factors, R, mode, out, ws, st);
+    (void)p; (void)X; (void)dims; (void)N; (void)factors; (void)R; (void)mode; (void)out; (void)ws; (void)st;
+    return fail(CPM_EUNSUPPORTED, "bf16 pair MTTKRP not built yet");
+}
+
+cpm_status validate_mttkrp(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                           int mode, const void *out, cpm_dtype dt, int64_t *total) {
+    cpm_status s = check_dtype(dt);
+    if (s) return s;
+    s = check_shape(dims, N, R, total, CPM_MAX_RANK);
+    if (s) return s;
+    if (dt == CPM_F64 && R > 128) return fail(CPM_EUNSUPPORTED, "float64 MTTKRP supports R <= 128");
+    if (!X) return fail(CPM_EINVAL, "X is null");
+    if (!out) return fail(CPM_EINVAL, "out is null");
+    if (!factors) return fail(CPM_EINVAL, "factors is null");
+    if (mode < 0 || mode >= N) return fail(CPM_EINVAL, "mode=%d outside [0, %d)", mode, N);
+    for (int k = 0; k < N; ++k)
+        if (k != mode && !factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    return CPM_OK;
+}
+
+size_t mttkrp_ws(const int64_t *dims, int N, int R, int mode, cpm_dtype dt) {
+    // The vector-load choice depends on X's alignment, not the sizes; plan
+    // with an aligned pointer (partial sizes do not depend on it).
+    Plan p = make_plan(dims, N, R, mode, dt, (const void *)(uintptr_t)4096);
+    return align_up(p.partial_bytes);
+}
+
+size_t max_mttkrp_ws(const int64_t *dims, int N, int R, cpm_dtype dt) {
+    size_t m = 0;
+    for (int n = 0; n < N; ++n) m = std::max(m, mttkrp_ws(dims, N, R, n, dt));
+    return m;
+}
+
+// ---------------------------- ALS / gradient -------------------------------
+struct SolveWs {
+    int *status;
+    double *xnorm2, *inner, *result;
+    double *grams, *gpart, *H, *L, *Lt;
+    void *M, *snap, *mws, *sumsq;
+    size_t need;
+};
+
+constexpr int64_t kGramRows = 256;
+constexpr int kSumsqBlocks = 1024;
+
+SolveWs layout_solve(const int64_t *dims, int N, int R, cpm_dtype dt, char *base, bool snapshot) {
+    SolveWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    int64_t maxI = 0, sumI = 0, maxblocks = 1;
+    for (int k = 0; k < N; ++k) {
+        maxI = std::max(maxI, dims[k]);
+        sumI += dims[k];
+        maxblocks = std::max(maxblocks, ceil_div(dims[k], kGramRows));
+    }
+    const size_t fz = dtype_f_bytes(dt);
+    w.status = (int *)take(sizeof(int));
+    w.xnorm2 = (double *)take(sizeof(double));
+    w.inner = (double *)take(sizeof(double));
+    w.result = (double *)take(sizeof(double));
+    w.grams = (double *)take((size_t)N * R * R * sizeof(double));
+    w.gpart = (double *)take((size_t)maxblocks * R * R * sizeof(double));
+    w.H = (double *)take((size_t)R * R * sizeof(double));
+    w.L = (double *)take((size_t)R * R * sizeof(double));
+    w.Lt = (double *)take((size_t)R * R * sizeof(double));
+    w.M = take((size_t)maxI * R * fz);
+    w.snap = snapshot ? take((size_t)sumI * R * fz) : nullptr;
+    w.sumsq = take((size_t)kSumsqBlocks * sizeof(double));
+    w.mws = take(max_mttkrp_ws(dims, N, R, dt));
+    w.need = off;
+    return w;
+}
+
+template <typename T>
+cpm_status gram_t(const T *U, int64_t I, int R, double *gpart, double *G, hipStream_t st) {
+    const int64_t blocks = ceil_div(I, kGramRows);
+    hipLaunchKernelGGL((k_gram_partial<T>), dim3((unsigned)blocks), dim3(kThreads), 0, st, U, I, R, kGramRows,
+                       gpart);
+    LAUNCH_CHECK("k_gram_partial");
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)ceil_div((int64_t)R * R, kThreads)), dim3(kThreads), 0, st,
+                       gpart, blocks, (int64_t)R * R, G);
+    LAUNCH_CHECK("k_sum_slices");
+    return CPM_OK;
+}
+
+cpm_status gram(const void *U, int64_t I, int R, cpm_dtype dt, double *gpart, double *G, hipStream_t st) {
+    if (dt == CPM_F64) return gram_t<double>((const double *)U, I, R, gpart, G, st);
+    return gram_t<float>((const float *)U, I, R, gpart, G, st);
+}
+
+cpm_status xnorm2_enqueue(const void *X, int64_t total, cpm_dtype dt, double *part, double *out, hipStream_t st) {
+    const int blocks = (int)std::min<int64_t>(kSumsqBlocks, ceil_div(total, kThreads));
+    if (dt == CPM_F32)
+        hipLaunchKernelGGL(k_sumsq_partial<CPM_F32>, dim3(blocks), dim3(kThreads), 0, st, X, total, part);
+    else if (dt == CPM_F64)
+        hipLaunchKernelGGL(k_sumsq_partial<CPM_F64>, dim3(blocks), dim3(kThreads), 0, st, X, total, part);
+    else
+        hipLaunchKernelGGL(k_sumsq_partial<CPM_BF16X2>, dim3(blocks), dim3(kThreads), 0, st, X, total, part);
+    LAUNCH_CHECK("k_sumsq_partial");
+    hipLaunchKernelGGL(k_sum_vector, dim3(1), dim3(kThreads), 0, st, part, blocks, out);
+    LAUNCH_CHECK("k_sum_vector");
+    return CPM_OK;
+}
+
+cpm_status hadamard_except(const double *grams, int N, int R, int skip, double *H, hipStream_t st) {
+    hipLaunchKernelGGL(k_hadamard_except, dim3((unsigned)ceil_div((int64_t)R * R, kThreads)), dim3(kThreads), 0,
+                       st, grams, N, R, skip, H);
+    LAUNCH_CHECK("k_hadamard_except");
+    return CPM_OK;
+}
+
+cpm_status dot_enqueue(const void *a, const void *b, int64_t n, cpm_dtype dt, double *out, hipStream_t st) {
+    if (dt == CPM_F64)
+        hipLaunchKernelGGL(k_dot<double>, dim3(1), dim3(kThreads), 0, st, (const double *)a, (const double *)b, n,
+                           out);
+    else
+        hipLaunchKernelGGL(k_dot<float>, dim3(1), dim3(kThreads), 0, st, (const float *)a, (const float *)b, n, out);
+    LAUNCH_CHECK("k_dot");
+    return CPM_OK;
+}
+
+cpm_status check_lds_for_cholesky(int R) {
+    int dev = 0, lds = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t need = (size_t)R * R * sizeof(double) + 64;
+    if ((size_t)lds < need)
+        return fail(CPM_EUNSUPPORTED, "R=%d needs %zu bytes of LDS for the Cholesky factorisation, device has %d",
+                    R, need, lds);
+    return CPM_OK;
+}
+
+}  // namespace
+
+// ================================ C-ABI ====================================
+extern "C" {
+
+int cpm_version(void) { return 10000; }
+
+const char *cpm_last_error(void) { return g_last_error.c_str(); }
+
+size_t cpm_mttkrp_workspace_bytes(const int64_t *dims, int N, int R, int mode, cpm_dtype dt) {
+    int64_t total;
+    std::string saved = g_last_error;
+    if (check_dtype(dt) || check_shape(dims, N, R, &total, CPM_MAX_RANK) || mode < 0 || mode >= N) {
+        g_last_error = saved;
+        return 0;
+    }
+    return mttkrp_ws(dims, N, R, mode, dt);
+}
+
+cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *factors, int R, int mode,
+                  void *out, cpm_dtype dt, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    int64_t total;
+    cpm_status s = validate_mttkrp(X, dims, N, factors, R, mode, out, dt, &total);
+    if (s) return s;
+    Plan p = make_plan(dims, N, R, mode, dt, X);
+    const size_t need = align_up(p.partial_bytes);
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    return run_mttkrp(p, X, dims, N, factors, R, mode, out, dt, workspace, stream);
+}
+
+size_t cpm_cp_als_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {
+    int64_t total;
+    std::string saved = g_last_error;
+    if (check_dtype(dt) || check_shape(dims, N, R, &total, CPM_MAX_RANK_SOLVE)) {
+        g_last_error = saved;
+        return 0;
+    }
+    return layout_solve(dims, N, R, dt, nullptr, true).need;
+}
+
+size_t cpm_cp_grad_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {
+    int64_t total;
+    std::string saved = g_last_error;
+    if (check_dtype(dt) || check_shape(dims, N, R, &total, CPM_MAX_RANK_SOLVE)) {
+        g_last_error = saved;
+        return 0;
+    }
+    return layout_solve(dims, N, R, dt, nullptr, false).need;
+}
+
+cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *factors, int R, cpm_dtype dt,
+                       double xnorm2, double *fit_out, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    int64_t total;
+    cpm_status s = check_dtype(dt);
+    if (s) return s;
+    s = check_shape(dims, N, R, &total, CPM_MAX_RANK_SOLVE);
+    if (s) return s;
+    if (!X) return fail(CPM_EINVAL, "X is null");
+    if (!factors) return fail(CPM_EINVAL, "factors is null");
+    for (int k = 0; k < N; ++k)
+        if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    const size_t need = layout_solve(dims, N, R, dt, nullptr, true).need;
+    if (!workspace || ws_bytes < need)
+        return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    s = check_lds_for_cholesky(R);
+    if (s) return s;
+    SolveWs w = layout_solve(dims, N, R, dt, (char *)workspace, true);
+    const size_t fz = dtype_f_bytes(dt);
+
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, stream, w.status);
+    LAUNCH_CHECK("k_clear_status");
+    size_t off = 0;
+    for (int k = 0; k < N; ++k) {
+        HIP_TRY(hipMemcpyAsync((char *)w.snap + off, factors[k], (size_t)dims[k] * R * fz, hipMemcpyDeviceToDevice,
+                               stream));
+        off += (size_t)dims[k] * R * fz;
+    }
+    for (int k = 0; k < N; ++k) {
+        s = gram(factors[k], dims[k], R, dt, w.gpart, w.grams + (size_t)k * R * R, stream);
+        if (s) return s;
+    }
+    const size_t lds_chol = (size_t)R * R * sizeof(double);
+    for (int n = 0; n < N; ++n) {
+        Plan p = make_plan(dims, N, R, n, dt, X);
+        s = run_mttkrp(p, X, dims, N, (const void *const *)factors, R, n, w.M, dt, w.mws, stream);
+        if (s) return s;
+        s = hadamard_except(w.grams, N, R, n, w.H, stream);
+        if (s) return s;
+        if (n == 0 && lds_chol > 65536)
+            HIP_TRY(hipFuncSetAttribute((const void *)k_cholesky, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds_chol));
+        hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kThreads), lds_chol, stream, w.H, R, w.L, w.Lt, w.status);
+        LAUNCH_CHECK("k_cholesky");
+        const unsigned blocks = (unsigned)ceil_div(dims[n], 4);
+        if (dt == CPM_F64)
+            hipLaunchKernelGGL(k_chol_solve_rows<double>, dim3(blocks), dim3(kThreads), 0, stream, w.L, w.Lt,
+                               w.status, (const double *)w.M, dims[n], R, (double *)factors[n]);
+        else
+            hipLaunchKernelGGL(k_chol_solve_rows<float>, dim3(blocks), dim3(kThreads), 0, stream, w.L, w.Lt,
+                               w.status, (const float *)w.M, dims[n], R, (float *)factors[n]);
+        LAUNCH_CHECK("k_chol_solve_rows");
+        s = gram(factors[n], dims[n], R, dt, w.gpart, w.grams + (size_t)n * R * R, stream);
+        if (s) return s;
+    }
+    if (fit_out) {
+        if (xnorm2 >= 0.0) {
+            hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, stream, w.xnorm2, xnorm2);
+            LAUNCH_CHECK("k_set_scalar");
+        } else {
+            s = xnorm2_enqueue(X, total, dt, (double *)w.sumsq, w.xnorm2, stream);
+            if (s) return s;
+        }
+        s = dot_enqueue(w.M, factors[N - 1], dims[N - 1] * R, dt, w.inner, stream);
+        if (s) return s;
+        hipLaunchKernelGGL(k_loss, dim3(1), dim3(kThreads), 0, stream, w.xnorm2, w.inner, w.grams, N, R, 1,
+                           w.result);
+        LAUNCH_CHECK("k_loss");
+    }
+    off = 0;
+    for (int k = 0; k < N; ++k) {
+        const int64_t cnt = dims[k] * R;
+        const unsigned blocks = (unsigned)std::min<int64_t>(1024, ceil_div(cnt, kThreads));
+        if (dt == CPM_F64)
+            hipLaunchKernelGGL(k_restore_if_failed<double>, dim3(blocks), dim3(kThreads), 0, stream, w.status,
+                               (const double *)((char *)w.snap + off), cnt, (double *)factors[k]);
+        else
+            hipLaunchKernelGGL(k_restore_if_failed<float>, dim3(blocks), dim3(kThreads), 0, stream, w.status,
+                               (const float *)((char *)w.snap + off), cnt, (float *)factors[k]);
+        LAUNCH_CHECK("k_restore_if_failed");
+        off += (size_t)cnt * fz;
+    }
+    int status_h = 0;
+    double result_h = 0.0;
+    HIP_TRY(hipMemcpyAsync(&status_h, w.status, sizeof(int), hipMemcpyDeviceToHost, stream));
+    if (fit_out) HIP_TRY(hipMemcpyAsync(&result_h, w.result, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (status_h) return fail(CPM_ENOTPD, "Hadamard product of Grams is not positive definite; factors restored");
+    if (fit_out) *fit_out = result_h;
+    return CPM_OK;
+}
+
+cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                   void *const *grads, double xnorm2, double *loss_dev, cpm_dtype dt, void *workspace,
+                   size_t ws_bytes, hipStream_t stream) {
+    int64_t total;
+    cpm_status s = check_dtype(dt);
+    if (s) return s;
+    s = check_shape(dims, N, R, &total, CPM_MAX_RANK_SOLVE);
+    if (s) return s;
+    if (!X) return fail(CPM_EINVAL, "X is null");
+    if (!factors) return fail(CPM_EINVAL, "factors is null");
+    for (int k = 0; k < N; ++k)
+        if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    const size_t need = layout_solve(dims, N, R, dt, nullptr, false).need;
+    if (!workspace || ws_bytes < need)
+        return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    SolveWs w = layout_solve(dims, N, R, dt, (char *)workspace, false);
+    for (int k = 0; k < N; ++k) {
+        s = gram(factors[k], dims[k], R, dt, w.gpart, w.grams + (size_t)k * R * R, stream);
+        if (s) return s;
+    }
+    for (int n = 0; n < N; ++n) {
+        const bool want_grad = grads && grads[n];
+        const bool want_inner = loss_dev && n == N - 1;
+        if (!want_grad && !want_inner) continue;
+        Plan p = make_plan(dims, N, R, n, dt, X);
+        s = run_mttkrp(p, X, dims, N, factors, R, n, w.M, dt, w.mws, stream);
+        if (s) return s;
+        if (want_inner) {
+            s = dot_enqueue(w.M, factors[n], dims[n] * R, dt, w.inner, stream);
+            if (s) return s;
+        }
+        if (want_grad) {
+            s = hadamard_except(w.grams, N, R, n, w.H, stream);
+            if (s) return s;
+            const unsigned blocks = (unsigned)ceil_div(dims[n] * R, kThreads);
+            if (dt == CPM_F64)
+                hipLaunchKernelGGL(k_grad<double>, dim3(blocks), dim3(kThreads), 0, stream,
+                                   (const double *)factors[n], w.H, (const double *)w.M, dims[n], R,
+                                   (double *)grads[n]);
+            else
+                hipLaunchKernelGGL(k_grad<float>, dim3(blocks), dim3(kThreads), 0, stream, (const float *)factors[n],
+                                   w.H, (const float *)w.M, dims[n], R, (float *)grads[n]);
+            LAUNCH_CHECK("k_grad");
+        }
+    }
+    if (loss_dev) {
+        if (xnorm2 >= 0.0) {
+            hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, stream, w.xnorm2, xnorm2);
+            LAUNCH_CHECK("k_set_scalar");
+        } else {
+            s = xnorm2_enqueue(X, total, dt, (double *)w.sumsq, w.xnorm2, stream);
+            if (s) return s;
+        }
+        hipLaunchKernelGGL(k_loss, dim3(1), dim3(kThreads), 0, stream, w.xnorm2, w.inner, w.grams, N, R, 0,
+                           loss_dev);
+        LAUNCH_CHECK("k_loss");
+    }
+    return CPM_OK;
+}
+
+size_t cpm_xnorm2_workspace_bytes(const int64_t *dims, int N, cpm_dtype dt) {
+    (void)dims;
+    (void)N;
+    (void)dt;
+    return align_up((size_t)kSumsqBlocks * sizeof(double));
+}
+
+cpm_status cpm_xnorm2(const void *X, const int64_t *dims, int N, cpm_dtype dt, double *out_dev, void *workspace,
+                      size_t ws_bytes, hipStream_t stream) {
+    int64_t total;
+    cpm_status s = check_dtype(dt);
+    if (s) return s;
+    s = check_shape(dims, N, 1, &total, CPM_MAX_RANK);
+    if (s) return s;
+    if (!X || !out_dev) return fail(CPM_EINVAL, "X or out_dev is null");
+    const size_t need = cpm_xnorm2_workspace_bytes(dims, N, dt);
+    if (!workspace || ws_bytes < need)
+        return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    return xnorm2_enqueue(X, total, dt, (double *)workspace, out_dev, stream);
+}
+
+cpm_status cpm_split_bf16(const float *x, int64_t count, uint16_t *planes, hipStream_t stream) {
+    if (!x || !planes) return fail(CPM_EINVAL, "x or planes is null");
+    if (count < 0) return fail(CPM_EINVAL, "count < 0");
+    if (count == 0) return CPM_OK;
+    const unsigned blocks = (unsigned)std::min<int64_t>(4096, ceil_div(count, kThreads));
+    hipLaunchKernelGGL(k_split_bf16, dim3(blocks), dim3(kThreads), 0, stream, x, count, planes);
+    LAUNCH_CHECK("k_split_bf16");
+    return CPM_OK;
+}
+
+cpm_status cpm_krp_rows(const void *const *mats, const int64_t *J, int Z, int R, int64_t j0, int64_t nrows,
+                        void *out, cpm_dtype dt, hipStream_t stream) {
+    if (dt != CPM_F32 && dt != CPM_F64) return fail(CPM_EINVAL, "cpm_krp_rows takes CPM_F32 or CPM_F64");
+    if (!mats || !J || !out) return fail(CPM_EINVAL, "null argument");
+    if (Z < 1 || Z > CPM_MAX_MODES) return fail(CPM_EINVAL, "Z=%d outside [1, %d]", Z, CPM_MAX_MODES);
+    if (R < 1 || R > CPM_MAX_RANK) return fail(R < 1 ? CPM_EINVAL : CPM_EUNSUPPORTED, "R=%d outside [1, %d]", R,
+                                              CPM_MAX_RANK);
+    int64_t rows = 1;
+    for (int z = 0; z < Z; ++z) {
+        if (!mats[z]) return fail(CPM_EINVAL, "mats[%d] is null", z);
+        if (J[z] < 1) return fail(CPM_EINVAL, "J[%d] < 1", z);
+        if (rows > ((int64_t)1 << 62) / J[z]) return fail(CPM_EUNSUPPORTED, "too many rows");
+        rows *= J[z];
+    }
+    if (j0 < 0 || nrows < 0 || j0 + nrows > rows) return fail(CPM_EINVAL, "row range outside the product");
+    if (nrows == 0) return CPM_OK;
+    if (ceil_div(nrows, 64) > INT32_MAX) return fail(CPM_EUNSUPPORTED, "nrows too large");
+    // mats[0] kr ... kr mats[Z-1]: the last matrix is the fastest index.
+    const int RP = (R + 15) / 16 * 16;
+    const unsigned blocks = (unsigned)ceil_div(nrows, 64);
+    if (dt == CPM_F32) {
+        Krp<float> k{};
+        k.rows = 1;
+        for (int z = Z - 1; z >= 0; --z) {
+            k.J[k.Z] = J[z];
+            k.stride[k.Z] = k.rows;
+            k.U[k.Z] = (const float *)mats[z];
+            k.rows *= J[z];
+            ++k.Z;
+        }
+        hipLaunchKernelGGL(k_krp_rows<float>, dim3(blocks), dim3(kThreads), 0, stream, k, R, RP, j0, nrows,
+                           (float *)out);
+    } else {
+        Krp<double> k{};
+        k.rows = 1;
+        for (int z = Z - 1; z >= 0; --z) {
+            k.J[k.Z] = J[z];
+            k.stride[k.Z] = k.rows;
+            k.U[k.Z] = (const double *)mats[z];
+            k.rows *= J[z];
+            ++k.Z;
+        }
+        hipLaunchKernelGGL(k_krp_rows<double>, dim3(blocks), dim3(kThreads), 0, stream, k, R, RP, j0, nrows,
+                           (double *)out);
+    }
+    LAUNCH_CHECK("k_krp_rows");
+    return CPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+the header declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1708_08976_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x100000  # never dereferenced: validation fails before any device access
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "cpmttkrp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\(", text)
+    skip = {"defined", "if", "extern"}
+    return sorted({n for n in names if n not in skip and not n.isupper()})
+
+
+def test_library_exports_every_declared_function():
+    lib = _abi.load()
+    declared = header_functions()
+    assert "mttkrp" in declared and "cp_als_step" in declared and "cp_grad" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(_abi.EXPORTS) == declared
+
+
+def test_version_and_error_string():
+    lib = _abi.load()
+    assert lib.cpm_version() >= 10000
+    assert isinstance(_abi.last_error(), str)
+
+
+def _dims(d):
+    return (ctypes.c_int64 * len(d))(*d)
+
+
+def _ptrs(n, null_at=None):
+    return (ctypes.c_void_p * n)(*[None if k == null_at else FAKE for k in range(n)])
+
+
+def call_mttkrp(dims, R=8, mode=0, X=FAKE, out=FAKE, dt=0, factors=None, ws=None, ws_len=0, N=None):
+    lib = _abi.load()
+    N = len(dims) if N is None else N
+    f = factors if factors is not None else _ptrs(max(1, len(dims)))
+    return lib.mttkrp(X, _dims(dims) if dims else None, N, f, R, mode, out, dt, ws, ws_len, None)
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(dims=(4, 5, 6), N=0), _abi.CPM_EINVAL),
+    (dict(dims=(4, 5, 6), N=13), _abi.CPM_EINVAL),
+    (dict(dims=(4, 5, 6), mode=3), _abi.CPM_EINVAL),
+    (dict(dims=(4, 5, 6), mode=-1), _abi.CPM_EINVAL),
+    (dict(dims=(4, 5, 6), R=0), _abi.CPM_EINVAL),
+    (dict(dims=(4, 5, 6), R=257), _abi.CPM_EUNSUPPORTED),
+    (dict(dims=(4, 0, 6)), _abi.CPM_EINVAL),
+    (dict(dims=(4, -3, 6)), _abi.CPM_EINVAL),
+    (dict(dims=(1 << 31, 1 << 31, 2)), _abi.CPM_EUNSUPPORTED),
+    (dict(dims=(4, 5, 6), X=None), _abi.CPM_EINVAL),
+    (dict(dims=(4, 5, 6), out=None), _abi.CPM_EINVAL),
+    (dict(dims=(4, 5, 6), dt=7), _abi.CPM_EINVAL),
+    (dict(dims=(4, 5, 6), dt=1, R=129), _abi.CPM_EUNSUPPORTED),
+])
+def test_mttkrp_rejects_bad_arguments(case, expect):
+    assert call_mttkrp(**case) == expect
+    assert _abi.last_error() != ""
+
+
+def test_mttkrp_rejects_null_factor_except_own_mode():
+    assert call_mttkrp((4, 5, 6), mode=0, factors=_ptrs(3, null_at=1)) == _abi.CPM_EINVAL
+    assert "factors[1]" in _abi.last_error()
+
+
+def test_mttkrp_workspace_checked_before_launch():
+    dims = (512, 512, 512)
+    need = _abi.mttkrp_workspace_bytes(dims, 32, 2, _abi.CPM_F32)
+    assert need > 0
+    assert call_mttkrp(dims, R=32, mode=2, ws=None, ws_len=0) == _abi.CPM_EWORKSPACE
+    assert call_mttkrp(dims, R=32, mode=2, ws=FAKE, ws_len=need - 1) == _abi.CPM_EWORKSPACE
+
+
+def test_workspace_queries():
+    lib = _abi.load()
+    assert lib.cpm_mttkrp_workspace_bytes(_dims((4, 5)), 2, 8, 5, 0) == 0  # bad mode -> 0
+    assert _abi.cp_als_workspace_bytes((60, 50, 40), 8, _abi.CPM_F64) > 0
+    assert _abi.cp_grad_workspace_bytes((64,) * 5, 32, _abi.CPM_F32) > 0
+    assert _abi.cp_als_workspace_bytes((60, 50, 40), 129, _abi.CPM_F32) == 0
+
+
+def test_solver_entry_points_validate():
+    lib = _abi.load()
+    d = _dims((4, 5, 6))
+    assert lib.cp_als_step(FAKE, d, 3, _ptrs(3), 129, 0, -1.0, None, FAKE, 1 << 30, None) == _abi.CPM_EUNSUPPORTED
+    assert lib.cp_als_step(FAKE, d, 3, _ptrs(3, null_at=2), 8, 0, -1.0, None, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.cp_als_step(FAKE, d, 3, _ptrs(3), 8, 0, -1.0, None, FAKE, 16, None) == _abi.CPM_EWORKSPACE
+    assert lib.cp_grad(FAKE, d, 3, _ptrs(3), 8, None, -1.0, None, 0, None, 0, None) == _abi.CPM_EWORKSPACE
+    assert lib.cp_grad(None, d, 3, _ptrs(3), 8, None, -1.0, None, 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.cpm_split_bf16(None, 10, FAKE, None) == _abi.CPM_EINVAL
+    assert lib.cpm_split_bf16(FAKE, -1, FAKE, None) == _abi.CPM_EINVAL
+    assert lib.cpm_krp_rows(_ptrs(2), _dims((3, 4)), 2, 5, 10, 5, FAKE, 0, None) == _abi.CPM_EINVAL
+    assert lib.cpm_krp_rows(_ptrs(2), _dims((3, 4)), 0, 5, 0, 5, FAKE, 0, None) == _abi.CPM_EINVAL
+    assert lib.cpm_xnorm2(FAKE, d, 3, 0, FAKE, None, 0, None) == _abi.CPM_EWORKSPACE

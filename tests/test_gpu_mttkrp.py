@@ -1,0 +1,157 @@
+"""GPU parity of MTTKRP against the FP64 oracle, through the C-ABI."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import (TOL, announce, make_case, oracle_abs_all_modes, oracle_all_modes, rel_err,
+                       rel_err_abs)
+from oracle import oracle as O
+from paper_1708_08976_amd import _abi, inputs
+
+pytestmark = pytest.mark.gpu
+
+# Shapes span several tiles with ragged tails, every shape class (mode 0,
+# internal modes with short and long left products, last mode), unaligned
+# rows (no 4-wide vector loads), single-index modes and N from 2 to 6.
+# Size-1 modes next to mode n make the left or right Khatri-Rao product a
+# single factor row rather than a row of ones.
+SHAPES = [
+    (37, 29, 41),
+    (64, 48, 80),
+    (96, 50, 70),
+    (5, 7, 3, 11, 13),
+    (16, 33, 2, 9),
+    (3, 130, 21),
+    (1, 17, 1, 19),
+    (200, 3),
+    (3, 200),
+    (12, 12, 12, 12, 12),
+    (6, 5, 4, 3, 2, 7),
+    (1000, 1, 1),
+    (1, 1, 1000),
+    (31, 1, 257),
+    (17, 19, 1),
+    (1, 40, 1, 1),
+    (20, 1, 30, 1),
+    (1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("R", [1, 13, 32, 70])
+def test_mttkrp_f32_all_modes(dims, R):
+    announce("mttkrp f32", dims, R)
+    X, U = make_case(dims, R, seed=sum(dims) + R)
+    refs = oracle_all_modes(X, dims, U)
+    absr = oracle_abs_all_modes(X, dims, U)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    for n in range(len(dims)):
+        out = torch.full((dims[n], R), float("nan"), device="cuda")
+        _abi.mttkrp(Xd, dims, Ud, n, out=out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.isfinite(got).all(), "unwritten output entries, mode %d" % n
+        err = rel_err_abs(got, refs[n], absr[n])
+        assert err <= TOL["f32"], (dims, R, n, err)
+
+
+@pytest.mark.parametrize("dims", [(60, 50, 40), (7, 9, 11, 5), (23, 40, 3)])
+@pytest.mark.parametrize("R", [8, 33, 128])
+def test_mttkrp_f64_all_modes(dims, R):
+    announce("mttkrp f64", dims, R)
+    X, U = make_case(dims, R, seed=3 + R, dtype=torch.float64)
+    refs = oracle_all_modes(X, dims, U)
+    absr = oracle_abs_all_modes(X, dims, U)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    for n in range(len(dims)):
+        got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
+        assert rel_err_abs(got, refs[n], absr[n]) <= TOL["f64"], (dims, R, n)
+
+
+@pytest.mark.parametrize("R", [200, 256])
+def test_mttkrp_f32_wide_rank_column_blocks(R):
+    dims = (40, 36, 30)
+    announce("mttkrp wide", dims, R)
+    X, U = make_case(dims, R, seed=R)
+    refs = oracle_all_modes(X, dims, U)
+    absr = oracle_abs_all_modes(X, dims, U)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    for n in range(3):
+        got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
+        assert rel_err_abs(got, refs[n], absr[n]) <= TOL["f32"], n
+
+
+def test_long_left_product_uses_several_chunks():
+    dims = (33, 47, 3, 2)  # IL for the last mode = 4653 > one l-chunk
+    X, U = make_case(dims, 24, seed=77)
+    refs = oracle_all_modes(X, dims, U)
+    absr = oracle_abs_all_modes(X, dims, U)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    for n in range(4):
+        got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
+        assert rel_err_abs(got, refs[n], absr[n]) <= TOL["f32"]
+
+
+def test_unaligned_base_pointer():
+    dims = (20, 16, 12)
+    X, U = make_case(dims, 8, seed=5)
+    big = torch.zeros(X.numel() + 1, dtype=torch.float32)
+    big[1:] = X.reshape(-1)
+    Xd = big.cuda()[1:]  # 4-byte offset: 16-byte vector loads must be avoided
+    Ud = [u.cuda() for u in U]
+    refs = oracle_all_modes(X, dims, U)
+    absr = oracle_abs_all_modes(X, dims, U)
+    for n in range(3):
+        got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
+        assert rel_err_abs(got, refs[n], absr[n]) <= TOL["f32"]
+
+
+def test_bitwise_reproducible():
+    dims = (64, 48, 80)
+    X, U = make_case(dims, 32, seed=11)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    for n in range(3):
+        a = _abi.mttkrp(Xd, dims, Ud, n)
+        b = _abi.mttkrp(Xd, dims, Ud, n)
+        assert torch.equal(a, b)
+
+
+def test_exact_rank_closed_form():
+    """For X = [[U]] the result is U_n times the Hadamard product of the
+    other Grams (a fact of the CP model, independent of both codes)."""
+    dims = (48, 40, 36)
+    R = 6
+    U = inputs.normal_factors(dims, R, seed=21, dtype=torch.float64)
+    X = inputs.cp_model_tensor(U)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    for n in range(3):
+        H = torch.ones(R, R, dtype=torch.float64)
+        for k in range(3):
+            if k != n:
+                H *= U[k].T @ U[k]
+        want = (U[n] @ H).numpy()
+        got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
+        assert rel_err(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("Js,R", [((7,), 5), ((3, 4), 16), ((5, 2, 3), 33), ((2, 3, 2, 5), 8)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_krp_rows_matches_oracle(Js, R, dtype):
+    mats = [torch.randn(J, R, dtype=dtype) for J in Js]
+    ref = O.krp_rows([m.numpy() for m in mats])
+    got = _abi.krp_rows([m.cuda() for m in mats]).cpu().numpy()
+    tol = 1e-6 if dtype == torch.float32 else 1e-15
+    np.testing.assert_allclose(got, ref, rtol=tol, atol=tol)
+    j0 = 3 if ref.shape[0] > 4 else 1
+    part = _abi.krp_rows([m.cuda() for m in mats], j0=j0, nrows=ref.shape[0] - j0 - 1).cpu().numpy()
+    np.testing.assert_allclose(part, ref[j0:-1], rtol=tol, atol=tol)
+
+
+def test_split_bf16_bit_exact_and_xnorm2():
+    x = inputs.normal_tensor((1000, 37), seed=9)
+    planes = _abi.split_bf16(x.cuda()).cpu()
+    want = inputs.split_bf16_planes(x)
+    assert torch.equal(planes, want)
+    dims = (1000, 37)
+    got = _abi.xnorm2(x.cuda(), dims).item()
+    assert got == pytest.approx(O.xnorm2(x.numpy().ravel(), dims), rel=1e-13)
