@@ -1,0 +1,266 @@
+"""Benchmark of the dense MTTKRP path on one MI355X.
+
+One step = the mode-0, mode-1 and mode-2 MTTKRP of a 512 x 512 x 512 float32
+tensor (a rank-32 CP model with N(0,1) factors plus 1% Gaussian noise) with
+rank R = 32, inputs resident in HBM.  `value` is the MTTKRP throughput of
+the whole step in GFLOP/s (2*I*R flops per mode).  The line also carries
+the roofline of the dominant launch (HBM-bound at R = 32), per-mode figures,
+and the FP64 oracle timed on the host cores as a CPU baseline.
+
+Extra measurements (on by default, --quick skips them): the CP-ALS sweep on
+the same tensor, the 256x256x512x32 correlation-style tensor at R = 64 in
+float32 and at R = 128 in split bf16 against float32, and CP-gradient
+evaluations per second on the 64^5 tensor.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="main workload only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1708_08976_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("per_launch", {}).get(kernel)
+
+
+class Timer:
+    """HIP events on the stream the library launches on."""
+
+    def __init__(self, torch, stream):
+        self.torch = torch
+        self.stream = stream
+
+    def event(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        return e
+
+
+def algo_bytes(dims, R, mode, xbytes):
+    I = 1
+    for d in dims:
+        I *= d
+    fb = sum(d * R * 4 for k, d in enumerate(dims) if k != mode)
+    return I * xbytes + fb + dims[mode] * R * 4
+
+
+def time_modes(torch, _abi, X, dims, U, outs, ws, dt, steps, warmup, stream):
+    """Per-mode average launch time (ms) and the whole-step time (ms)."""
+    timer = Timer(torch, stream)
+    N = len(dims)
+
+    def one_step(evs=None):
+        for n in range(N):
+            if evs is not None:
+                evs[n][0].append(timer.event())
+            _abi.mttkrp(X, dims, U, n, out=outs[n], dtype=dt, workspace=ws)
+            if evs is not None:
+                evs[n][1].append(timer.event())
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    evs = [([], []) for _ in range(N)]
+    t0 = timer.event()
+    for _ in range(steps):
+        one_step(evs)
+    t1 = timer.event()
+    torch.cuda.synchronize()
+    step_ms = t0.elapsed_time(t1) / steps
+    per_mode = [sum(a.elapsed_time(b) for a, b in zip(*evs[n])) / steps for n in range(N)]
+    return step_ms, per_mode
+
+
+def shape_class(dims, n):
+    if n == 0:
+        return "mode0 (contiguous output index, right-first)"
+    if n == len(dims) - 1:
+        return "last mode (contracted index contiguous, left-first)"
+    return "internal (fused 2-step)"
+
+
+def cpu_baseline(X, dims, U):
+    """The FP64 oracle on the host cores, all modes of the main tensor once."""
+    import numpy as np
+
+    from oracle import oracle as O
+    Xh = X.cpu().numpy().ravel()
+    Uh = [u.cpu().numpy().astype(np.float64) for u in U]
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    t0 = time.perf_counter()
+    for n in range(len(dims)):
+        O.mttkrp(Xh, dims, Uh, n, nthreads=threads)
+    dt = time.perf_counter() - t0
+    I = Xh.size
+    R = Uh[0].shape[1]
+    flops = len(dims) * 2.0 * I * R
+    return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "all %d modes of the full %s tensor, R=%d, once (%.1f s)" % (
+                len(dims), "x".join(map(str, dims)), R, dt)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d (WORLD_SIZE=%d) is not supported"
+              % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1708_08976_amd import _abi, inputs
+    _abi.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    # ---------------- main workload: 512^3 float32, R = 32 ----------------
+    dims, R = (512, 512, 512), 32
+    X, _ = inputs.noisy_low_rank(dims, R, seed_factors=3, seed_noise=4, eta=0.01, device="cuda")
+    U = inputs.normal_factors(dims, R, seed=5, device="cuda")
+    outs = [torch.empty((d, R), device=dev) for d in dims]
+    ws = torch.empty(max(_abi.mttkrp_workspace_bytes(dims, R, n, _abi.CPM_F32) for n in range(3)) + 256,
+                     dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    step_ms, per_mode = time_modes(torch, _abi, X, dims, U, outs, ws, _abi.CPM_F32, args.steps, args.warmup,
+                                   stream)
+    wall = time.perf_counter() - wall0
+    I = 512 ** 3
+    flops_mode = 2.0 * I * R
+    value = 3 * flops_mode / (step_ms / 1e3) / 1e9
+    modes = []
+    for n in range(3):
+        b = algo_bytes(dims, R, n, 4)
+        gbs = b / (per_mode[n] / 1e3) / 1e9
+        modes.append({"mode": n, "class": shape_class(dims, n), "us": round(per_mode[n] * 1e3, 2),
+                      "GFLOP/s": round(flops_mode / (per_mode[n] / 1e3) / 1e9, 1),
+                      "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+    dom = max(range(3), key=lambda n: per_mode[n])
+    dom_bytes = algo_bytes(dims, R, dom, 4)
+    achieved = dom_bytes / (per_mode[dom] / 1e3) / 1e9
+    kname = "mttkrp_mode%d" % dom
+    roofline = {"bound": "hbm", "kernel": kname + " (contraction + split reduction, one C-ABI call)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes": dom_bytes,
+                "traffic": measured_traffic("fp32_512cube_r32", kname)}
+
+    line = {"metric": "MTTKRP GFLOP/s (all modes) + HBM GB/s, % of roofline", "value": round(value, 1),
+            "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(step_ms, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "512x512x512 float32 tensor (rank-32 CP model, N(0,1) factors, 1% noise), "
+                                   "R=32, MTTKRP of modes 0,1,2 per step", "dims": list(dims), "R": R},
+            "roofline": roofline, "per_mode": modes, "wall_s_timed": round(wall, 3)}
+
+    if not args.quick:
+        line["extra"] = extra_measurements(torch, _abi, inputs, X, dims, U, stream)
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(X, dims, U)
+    print(json.dumps(line), flush=True)
+
+
+def extra_measurements(torch, _abi, inputs, X2, dims2, U2, stream):
+    out = {}
+    dev = X2.device
+    timer = Timer(torch, stream)
+
+    # CP-ALS sweep on the main tensor (MTTKRP x3 + FP64 Grams/Cholesky/solves).
+    Ua = [u.clone() for u in U2]
+    ws = torch.empty(_abi.cp_als_workspace_bytes(dims2, 32, _abi.CPM_F32), dtype=torch.uint8, device=dev)
+    xn = float(_abi.xnorm2(X2, dims2).item())
+    for _ in range(2):
+        _abi.cp_als_step(X2, dims2, Ua, xnorm2=xn, want_fit=True, workspace=ws)
+    reps = 5
+    t0 = timer.event()
+    for _ in range(reps):
+        fit = _abi.cp_als_step(X2, dims2, Ua, xnorm2=xn, want_fit=True, workspace=ws)
+    t1 = timer.event()
+    torch.cuda.synchronize()
+    out["cp_als_sweep_512cube_r32"] = {"ms": round(t0.elapsed_time(t1) / reps, 3), "fit": round(fit, 6)}
+
+    # 256x256x512x32 correlation-style tensor: float32 at R=64, split bf16 vs float32 at R=128.
+    dims3 = (256, 256, 512, 32)
+    X3 = inputs.symmetric_pair_tensor(dims3, seed=6, device="cuda")
+    for R, tag in [(64, "fp32_r64")]:
+        U3 = inputs.normal_factors(dims3, R, seed=7, device="cuda")
+        outs = [torch.empty((d, R), device=dev) for d in dims3]
+        ws3 = torch.empty(max(_abi.mttkrp_workspace_bytes(dims3, R, n, _abi.CPM_F32) for n in range(4)) + 256,
+                          dtype=torch.uint8, device=dev)
+        step_ms, per_mode = time_modes(torch, _abi, X3, dims3, U3, outs, ws3, _abi.CPM_F32, 5, 1, stream)
+        I = 256 * 256 * 512 * 32
+        fl = 2.0 * I * R
+        out["sym4d_" + tag] = {
+            "ms_all_modes": round(step_ms, 3),
+            "per_mode_us": [round(t * 1e3, 1) for t in per_mode],
+            "per_mode_TFLOP/s": [round(fl / (t / 1e3) / 1e12, 2) for t in per_mode],
+            "fp32_mfma_frac": [round(fl / (t / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4) for t in per_mode]}
+        del U3, outs, ws3
+    del X3
+    torch.cuda.empty_cache()
+
+    # CP gradient evaluations per second on 64^5 (float32, R=32).
+    dims5, R5 = (64,) * 5, 32
+    X5, _ = inputs.noisy_low_rank(dims5, R5, seed_factors=9, seed_noise=10, eta=0.05, device="cuda")
+    U5 = inputs.normal_factors(dims5, R5, seed=11, device="cuda")
+    x5 = float(_abi.xnorm2(X5, dims5).item())
+    ws5 = torch.empty(_abi.cp_grad_workspace_bytes(dims5, R5, _abi.CPM_F32), dtype=torch.uint8, device=dev)
+    grads = [torch.empty_like(u) for u in U5]
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    for _ in range(2):
+        _abi.cp_grad(X5, dims5, U5, grads=grads, xnorm2=x5, loss=loss, workspace=ws5)
+    reps = 5
+    t0 = timer.event()
+    for _ in range(reps):
+        _abi.cp_grad(X5, dims5, U5, grads=grads, xnorm2=x5, loss=loss, workspace=ws5)
+    t1 = timer.event()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    out["cp_grad_64p5_r32_fp32"] = {"ms_per_eval": round(ms, 3), "evals_per_s": round(1e3 / ms, 2),
+                                    "hbm_roofline_evals_per_s": round(HBM_PEAK_GBS * 1e9 / (5 * 4 * 64 ** 5), 1)}
+    del X5
+    torch.cuda.empty_cache()
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -78,19 +78,22 @@ enum Kind { kLeft = 0, kRight = 1, kBf16Left = 2, kBf16Right = 3 };
 struct Plan {
     Kind kind;
     int64_t IL, In, IR, J;
-    int NB, MB, WI, ncb;      // n-blocks per column block, m-blocks, wave rows, column blocks
-    int LC;                   // left: l-chunk; right: r-chunk rows
-    int64_t nlc, ups, units;  // left: chunks per slab, units per split, units per row tile
-    int64_t S, ntiles;        // splits, row tiles (left) / column tiles (right)
-    int64_t rps;              // right: rows per split
+    int NB, MB, ncb;          // n-blocks per column block, m-blocks (right: MJ), column blocks
+    int p;                    // left: inner modes [0, p); right: inner modes [mode+1, p)
+    int64_t G_in, G_out;      // inner rows of the contracted product; left: outer left extent
+    int64_t n_outer;          // outer blocks
+    int SPB, LC;              // steps per block per wave, inner chunk (64 * SPB)
+    int64_t nlc, bps, S;      // inner chunks, blocks per split, splits
+    int64_t ntiles;           // row tiles (left) / j tiles (right)
     bool v4;
     size_t lds;
     bool reduce;              // partials need the reduction kernel
     size_t partial_bytes;
+    int64_t max_offset;       // largest byte offset a buffer load uses (must stay below 2^32 - 256)
 };
 
-constexpr int kTargetGroups = 1024;
-constexpr size_t kLdsBudget = 65536;
+constexpr int kTargetGroups = 512;        // about two resident work-groups per CU
+constexpr size_t kTileBytes = 78 * 1024;   // LDS for the resident Khatri-Rao tile
 
 int pow2_at_least(int v) {
     int p = 1;
@@ -113,7 +116,8 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
         return p;
     }
     const bool left = p.IL >= 16;
-    const int nbmax = (dt == CPM_F64) ? 4 : 8;
+    const bool dbl = dt == CPM_F64;
+    const int nbmax = dbl ? 2 : 8;
     int nb = RPtot / 16;
     if (nb <= nbmax) {
         p.NB = pow2_at_least(nb);
@@ -123,194 +127,201 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
         p.ncb = (int)ceil_div(nb, nbmax);
     }
     const int RP = p.NB * 16;
+    const int pitch = RP + 4;
+    const int64_t lcmax = std::max<int64_t>(64, std::min<int64_t>(512, (int64_t)(kTileBytes / (pitch * sz)) / 64 * 64));
+    // Inner part of the contracted product: consecutive modes starting next
+    // to the stride-1 end, as many as fit in one tile (at least one mode;
+    // a single mode longer than a tile is cut into chunks).
+    auto pick_inner = [&](int first, int last, int64_t &G) {
+        int q = first;
+        G = 1;
+        while (q < last && G * dims[q] <= lcmax) G *= dims[q++];
+        if (q == first && q < last) G = dims[q++];
+        return q;
+    };
     if (left) {
         p.kind = kLeft;
-        const int budget_mb = (dt == CPM_F64) ? 8 : 16;
-        p.MB = std::min(4, std::max(1, budget_mb / p.NB));
+        p.MB = dbl ? 2 : std::min(4, std::max(1, 16 / p.NB));
         while (p.MB > 1 && 16 * p.MB / 2 >= p.In) p.MB /= 2;
-        p.WI = 1;
-        const int pitch = RP + 4;
-        const int64_t il16 = ceil_div(p.IL, 16) * 16;
+        p.p = pick_inner(0, mode, p.G_in);
+        p.G_out = p.IL / p.G_in;
+        p.n_outer = p.G_out * p.IR;
+        p.LC = (int)std::min<int64_t>(lcmax, ceil_div(p.G_in, 64) * 64);
+        p.SPB = p.LC / 64;
+        p.nlc = ceil_div(p.G_in, p.LC);
+        p.ntiles = ceil_div(p.In, 16 * p.MB);
         const size_t red = (size_t)4 * p.MB * p.NB * 256 * sz;
-        if ((size_t)il16 * pitch * sz <= kLdsBudget && il16 <= 1024) {
-            p.LC = (int)il16;
-            p.nlc = 1;
-        } else {
-            int lc = (int)(kLdsBudget / (2 * pitch * sz)) / 16 * 16;
-            lc = std::max(16, std::min(lc, 512));
-            p.LC = lc;
-            p.nlc = ceil_div(p.IL, lc);
-        }
-        const size_t tile = (size_t)(p.nlc == 1 ? 1 : 2) * p.LC * pitch * sz;
-        p.lds = std::max(tile, red);
-        p.ntiles = ceil_div(p.In, 16 * p.MB * p.WI);
-        p.units = p.IR * p.nlc;
-        int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.ncb));
-        S = std::min(S, p.units);
-        p.ups = ceil_div(p.units, S);
-        p.S = ceil_div(p.units, p.ups);
-        p.v4 = (p.IL % 4 == 0) && ((uintptr_t)X % (4 * sz) == 0);
+        p.lds = std::max((size_t)p.LC * pitch * sz, red);
+        int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.nlc * p.ncb));
+        S = std::min(S, p.n_outer);
+        p.bps = ceil_div(p.n_outer, S);
+        p.S = ceil_div(p.n_outer, p.bps);
+        p.v4 = (p.G_in % 4 == 0) && ((uintptr_t)X % (4 * sz) == 0);
+        p.max_offset = (15 * p.IL + p.G_in + 4) * (int64_t)sz;  // lane offsets within one m-block
         p.J = p.In;
-        p.reduce = p.S > 1;
-        p.partial_bytes = p.reduce ? (size_t)p.S * p.In * R * sz : 0;
+        p.reduce = p.S * p.nlc > 1;
+        p.partial_bytes = p.reduce ? (size_t)p.S * p.nlc * p.In * R * sz : 0;
     } else {
         p.kind = kRight;
         p.J = p.In * p.IL;
-        const int mjmax = (dt == CPM_F64) ? (p.NB <= 1 ? 2 : 1) : (p.NB <= 2 ? 2 : 1);
-        p.MB = (p.J <= 64) ? 1 : mjmax;  // MJ
-        p.WI = 4;
-        const int pitch = RP + 16;
-        int rc = (int)(kLdsBudget / (2 * pitch * sz)) / 16 * 16;
-        rc = std::max(16, std::min(rc, 256));
-        p.LC = rc;
-        const size_t red = (size_t)4096 * p.MB * p.NB * sz;
-        p.lds = std::max((size_t)2 * rc * pitch * sz, red);
+        p.MB = (dbl || p.NB > 1 || p.J <= 64) ? 1 : 2;  // MJ
+        p.p = pick_inner(mode + 1, N, p.G_in);
+        p.n_outer = p.IR / p.G_in;
+        p.LC = (int)std::min<int64_t>(lcmax, ceil_div(p.G_in, 64) * 64);
+        p.SPB = p.LC / 64;
+        p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.J, 64 * p.MB);
-        int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.ncb));
-        S = std::min(S, ceil_div(p.IR, 4));
-        p.rps = ceil_div(ceil_div(p.IR, S), 4) * 4;
-        p.S = ceil_div(p.IR, p.rps);
+        const size_t red = (size_t)4 * p.MB * 4 * p.NB * 256 * sz;
+        p.lds = std::max((size_t)p.LC * pitch * sz, red);
+        int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.nlc * p.ncb));
+        S = std::min(S, p.n_outer);
+        p.bps = ceil_div(p.n_outer, S);
+        p.S = ceil_div(p.n_outer, p.bps);
         p.v4 = (p.J % 4 == 0) && ((uintptr_t)X % (4 * sz) == 0);
-        p.reduce = p.S > 1 || mode > 0;  // mode > 0: the multi-TTV with K_L runs in the reduction
-        p.partial_bytes = p.reduce ? (size_t)p.S * p.J * R * sz : 0;
+        p.max_offset = ((16 * (int64_t)p.SPB) * p.J + 64 * p.MB + 4) * (int64_t)sz;  // within one wave's rows
+        p.reduce = p.S * p.nlc > 1 || mode > 0;  // mode > 0: the multi-TTV with K_L runs in the reduction
+        p.partial_bytes = p.reduce ? (size_t)p.S * p.nlc * p.J * R * sz : 0;
     }
     return p;
 }
 
+// ----------------------------- kernel dispatch -----------------------------
+template <typename T, int NB, int MB>
+void launch_left_t(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kout, int R, T *partial,
+                   hipStream_t st) {
+    dim3 grid((unsigned)p.ntiles, (unsigned)(p.S * p.nlc), (unsigned)p.ncb);
+    if (p.v4)
+        hipLaunchKernelGGL((k_contract_left<T, NB, MB, true>), grid, dim3(kThreads), p.lds, st, X, p.G_in, p.G_out,
+                           p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+    else
+        hipLaunchKernelGGL((k_contract_left<T, NB, MB, false>), grid, dim3(kThreads), p.lds, st, X, p.G_in, p.G_out,
+                           p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+}
+
+template <typename T, int NB>
+void launch_left_m(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kout, int R, T *partial,
+                   hipStream_t st) {
+    switch (p.MB) {
+    case 1: launch_left_t<T, NB, 1>(p, X, kin, kout, R, partial, st); break;
+    case 2: launch_left_t<T, NB, 2>(p, X, kin, kout, R, partial, st); break;
+    default: launch_left_t<T, NB, 4>(p, X, kin, kout, R, partial, st); break;
+    }
+}
+
 template <typename T>
-Krp<T> make_krp(const void *const *factors, const int64_t *dims, int first, int last, bool &ok) {
-    // modes first..last-1, fastest first
+void launch_left(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kout, int R, T *partial,
+                 hipStream_t st);
+template <>
+void launch_left<float>(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
+                        float *partial, hipStream_t st) {
+    switch (p.NB) {
+    case 1: launch_left_m<float, 1>(p, X, kin, kout, R, partial, st); break;
+    case 2: launch_left_m<float, 2>(p, X, kin, kout, R, partial, st); break;
+    case 4: launch_left_m<float, 4>(p, X, kin, kout, R, partial, st); break;
+    default: launch_left_m<float, 8>(p, X, kin, kout, R, partial, st); break;
+    }
+}
+template <>
+void launch_left<double>(const Plan &p, const double *X, const Krp<double> &kin, const Krp<double> &kout, int R,
+                         double *partial, hipStream_t st) {
+    // float64: MB <= 2, NB <= 2
+    if (p.NB == 1) {
+        if (p.MB == 1) launch_left_t<double, 1, 1>(p, X, kin, kout, R, partial, st);
+        else launch_left_t<double, 1, 2>(p, X, kin, kout, R, partial, st);
+    } else {
+        if (p.MB == 1) launch_left_t<double, 2, 1>(p, X, kin, kout, R, partial, st);
+        else launch_left_t<double, 2, 2>(p, X, kin, kout, R, partial, st);
+    }
+}
+
+template <typename T, int NB, int MJ>
+void launch_right_t(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kout, int R, T *partial,
+                    hipStream_t st) {
+    dim3 grid((unsigned)p.ntiles, (unsigned)(p.S * p.nlc), (unsigned)p.ncb);
+    if (p.v4)
+        hipLaunchKernelGGL((k_contract_right<T, NB, MJ, true>), grid, dim3(kThreads), p.lds, st, X, p.J, p.G_in,
+                           p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+    else
+        hipLaunchKernelGGL((k_contract_right<T, NB, MJ, false>), grid, dim3(kThreads), p.lds, st, X, p.J, p.G_in,
+                           p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+}
+
+template <typename T>
+void launch_right(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kout, int R, T *partial,
+                  hipStream_t st);
+template <>
+void launch_right<float>(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
+                         float *partial, hipStream_t st) {
+    switch (p.NB) {
+    case 1:
+        if (p.MB == 2) launch_right_t<float, 1, 2>(p, X, kin, kout, R, partial, st);
+        else launch_right_t<float, 1, 1>(p, X, kin, kout, R, partial, st);
+        break;
+    case 2: launch_right_t<float, 2, 1>(p, X, kin, kout, R, partial, st); break;
+    case 4: launch_right_t<float, 4, 1>(p, X, kin, kout, R, partial, st); break;
+    default: launch_right_t<float, 8, 1>(p, X, kin, kout, R, partial, st); break;
+    }
+}
+template <>
+void launch_right<double>(const Plan &p, const double *X, const Krp<double> &kin, const Krp<double> &kout, int R,
+                          double *partial, hipStream_t st) {
+    if (p.NB == 1) launch_right_t<double, 1, 1>(p, X, kin, kout, R, partial, st);
+    else launch_right_t<double, 2, 1>(p, X, kin, kout, R, partial, st);
+}
+
+// Enqueue one MTTKRP (arguments already validated).
+// Khatri-Rao descriptor over a list of modes, fastest first.
+template <typename T>
+Krp<T> krp_of(const void *const *factors, const int64_t *dims, const int *modes, int count) {
     Krp<T> k{};
     k.Z = 0;
     k.rows = 1;
-    ok = true;
-    for (int m = first; m < last; ++m) {
+    for (int i = 0; i < count; ++i) {
+        const int m = modes[i];
         k.J[k.Z] = dims[m];
         k.stride[k.Z] = k.rows;
         k.U[k.Z] = reinterpret_cast<const T *>(factors[m]);
-        if (!factors[m]) ok = false;
         k.rows *= dims[m];
         ++k.Z;
     }
     return k;
 }
 
-// ----------------------------- kernel dispatch -----------------------------
-template <typename T, int NB, int MB, bool V4>
-void launch_left_t(const Plan &p, const T *X, const Krp<T> &kl, const Krp<T> &kr, int R, T *partial,
-                   hipStream_t st) {
-    dim3 grid((unsigned)p.ntiles, (unsigned)p.S, (unsigned)p.ncb);
-    hipLaunchKernelGGL((k_contract_left<T, NB, MB, V4>), grid, dim3(kThreads), p.lds, st, X, p.IL, p.In, p.IR,
-                       kl, kr, R, p.LC, p.WI, p.nlc, p.ups, p.units, partial);
-}
-
-template <typename T, int NB, int MB>
-void launch_left_v(const Plan &p, const T *X, const Krp<T> &kl, const Krp<T> &kr, int R, T *partial,
-                   hipStream_t st) {
-    if (p.v4) launch_left_t<T, NB, MB, true>(p, X, kl, kr, R, partial, st);
-    else launch_left_t<T, NB, MB, false>(p, X, kl, kr, R, partial, st);
-}
-
-template <typename T, int NB>
-void launch_left_m(const Plan &p, const T *X, const Krp<T> &kl, const Krp<T> &kr, int R, T *partial,
-                   hipStream_t st) {
-    switch (p.MB) {
-    case 1: launch_left_v<T, NB, 1>(p, X, kl, kr, R, partial, st); break;
-    case 2: launch_left_v<T, NB, 2>(p, X, kl, kr, R, partial, st); break;
-    default: launch_left_v<T, NB, 4>(p, X, kl, kr, R, partial, st); break;
-    }
-}
-
-template <typename T>
-void launch_left(const Plan &p, const T *X, const Krp<T> &kl, const Krp<T> &kr, int R, T *partial,
-                 hipStream_t st);
-template <>
-void launch_left<float>(const Plan &p, const float *X, const Krp<float> &kl, const Krp<float> &kr, int R,
-                        float *partial, hipStream_t st) {
-    switch (p.NB) {
-    case 1: launch_left_m<float, 1>(p, X, kl, kr, R, partial, st); break;
-    case 2: launch_left_m<float, 2>(p, X, kl, kr, R, partial, st); break;
-    case 4: launch_left_m<float, 4>(p, X, kl, kr, R, partial, st); break;
-    default: launch_left_m<float, 8>(p, X, kl, kr, R, partial, st); break;
-    }
-}
-template <>
-void launch_left<double>(const Plan &p, const double *X, const Krp<double> &kl, const Krp<double> &kr, int R,
-                         double *partial, hipStream_t st) {
-    switch (p.NB) {
-    case 1: launch_left_m<double, 1>(p, X, kl, kr, R, partial, st); break;
-    case 2: launch_left_m<double, 2>(p, X, kl, kr, R, partial, st); break;
-    default: launch_left_m<double, 4>(p, X, kl, kr, R, partial, st); break;
-    }
-}
-
-template <typename T, int NB, int MJ, bool V4>
-void launch_right_t(const Plan &p, const T *X, const Krp<T> &kr, int R, T *partial, hipStream_t st) {
-    dim3 grid((unsigned)p.ntiles, (unsigned)p.S, (unsigned)p.ncb);
-    hipLaunchKernelGGL((k_contract_right<T, NB, MJ, V4>), grid, dim3(kThreads), p.lds, st, X, p.J, p.IR, kr, R,
-                       p.LC, p.rps, partial);
-}
-
-template <typename T, int NB, int MJ>
-void launch_right_v(const Plan &p, const T *X, const Krp<T> &kr, int R, T *partial, hipStream_t st) {
-    if (p.v4) launch_right_t<T, NB, MJ, true>(p, X, kr, R, partial, st);
-    else launch_right_t<T, NB, MJ, false>(p, X, kr, R, partial, st);
-}
-
-template <typename T, int NB>
-void launch_right_m(const Plan &p, const T *X, const Krp<T> &kr, int R, T *partial, hipStream_t st) {
-    if (p.MB == 2) launch_right_v<T, NB, 2>(p, X, kr, R, partial, st);
-    else launch_right_v<T, NB, 1>(p, X, kr, R, partial, st);
-}
-
-template <typename T>
-void launch_right(const Plan &p, const T *X, const Krp<T> &kr, int R, T *partial, hipStream_t st);
-template <>
-void launch_right<float>(const Plan &p, const float *X, const Krp<float> &kr, int R, float *partial,
-                         hipStream_t st) {
-    switch (p.NB) {
-    case 1: launch_right_m<float, 1>(p, X, kr, R, partial, st); break;
-    case 2: launch_right_m<float, 2>(p, X, kr, R, partial, st); break;
-    case 4: launch_right_m<float, 4>(p, X, kr, R, partial, st); break;
-    default: launch_right_m<float, 8>(p, X, kr, R, partial, st); break;
-    }
-}
-template <>
-void launch_right<double>(const Plan &p, const double *X, const Krp<double> &kr, int R, double *partial,
-                          hipStream_t st) {
-    switch (p.NB) {
-    case 1: launch_right_m<double, 1>(p, X, kr, R, partial, st); break;
-    case 2: launch_right_m<double, 2>(p, X, kr, R, partial, st); break;
-    default: launch_right_m<double, 4>(p, X, kr, R, partial, st); break;
-    }
-}
-
 // Enqueue one MTTKRP (arguments already validated).
 template <typename T>
 cpm_status run_mttkrp_t(const Plan &p, const void *Xv, const int64_t *dims, int N, const void *const *factors,
                         int R, int mode, void *outv, void *ws, hipStream_t st) {
-    bool ok1, ok2;
-    Krp<T> kl = make_krp<T>(factors, dims, 0, mode, ok1);
-    Krp<T> kr = make_krp<T>(factors, dims, mode + 1, N, ok2);
-    if (!ok1 || !ok2) return fail(CPM_EINVAL, "a factor pointer other than factors[mode] is null");
+    int in_modes[CPM_MAX_MODES], out_modes[CPM_MAX_MODES], left_modes[CPM_MAX_MODES];
+    int nin = 0, nout = 0, nleft = 0;
+    for (int k = 0; k < mode; ++k) left_modes[nleft++] = k;
+    if (p.kind == kLeft) {
+        for (int k = 0; k < p.p; ++k) in_modes[nin++] = k;
+        for (int k = p.p; k < mode; ++k) out_modes[nout++] = k;
+        for (int k = mode + 1; k < N; ++k) out_modes[nout++] = k;
+    } else {
+        for (int k = mode + 1; k < p.p; ++k) in_modes[nin++] = k;
+        for (int k = p.p; k < N; ++k) out_modes[nout++] = k;
+    }
+    const Krp<T> kin = krp_of<T>(factors, dims, in_modes, nin);
+    const Krp<T> kout = krp_of<T>(factors, dims, out_modes, nout);
     const T *X = reinterpret_cast<const T *>(Xv);
     T *out = reinterpret_cast<T *>(outv);
     T *partial = p.reduce ? reinterpret_cast<T *>(ws) : out;
     if (p.kind == kLeft) {
-        launch_left<T>(p, X, kl, kr, R, partial, st);
+        launch_left<T>(p, X, kin, kout, R, partial, st);
         LAUNCH_CHECK("k_contract_left");
     } else {
-        launch_right<T>(p, X, kr, R, partial, st);
+        launch_right<T>(p, X, kin, kout, R, partial, st);
         LAUNCH_CHECK("k_contract_right");
     }
     if (p.reduce) {
         const int64_t total = p.In * R;
         const int64_t rows_per_slice = (p.kind == kLeft) ? p.In : p.J;
+        // right-first for mode > 0: the multi-TTV with K_L (all left modes)
+        Krp<T> kred = krp_of<T>(factors, dims, left_modes, p.kind == kLeft ? 0 : nleft);
         const int64_t il = (p.kind == kLeft) ? 1 : p.IL;
-        Krp<T> kred = kl;
-        if (p.kind == kLeft) kred.Z = 0;  // K_L was applied inside the contraction
         hipLaunchKernelGGL((k_reduce<T, T>), dim3((unsigned)ceil_div(total, 64)), dim3(kThreads), 0, st, partial,
-                           p.S, rows_per_slice, p.In, il, kred, R, out);
+                           p.S * p.nlc, rows_per_slice, p.In, il, kred, R, out);
         LAUNCH_CHECK("k_reduce");
     }
     return CPM_OK;
@@ -481,6 +492,9 @@ cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *
     cpm_status s = validate_mttkrp(X, dims, N, factors, R, mode, out, dt, &total);
     if (s) return s;
     Plan p = make_plan(dims, N, R, mode, dt, X);
+    if (p.max_offset >= (int64_t)0xFFFFFF00LL)
+        return fail(CPM_EUNSUPPORTED, "mode %d: entries %lld apart along mode %d exceed the 4 GiB reach of one "
+                    "buffer resource", mode, (long long)p.IL, mode);
     const size_t need = align_up(p.partial_bytes);
     if (need > 0 && (!workspace || ws_bytes < need))
         return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);

@@ -112,6 +112,171 @@ __device__ inline void build_krp_rows(const Krp<T> &k, int R, int coff, int RP, 
 }
 
 // ---------------------------------------------------------------------------
+// Buffer loads.  A buffer resource holds a base address and a byte range; a
+// load whose byte offset falls outside the range returns zero instead of
+// touching memory.  The kernels give a lane with nothing to load the offset
+// kNoLoad, so every load is issued unconditionally (no branch around it) and
+// inactive lanes read zeros.  Offsets are unsigned 32-bit: callers keep
+// every live offset below kRsrcRange.
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kRsrcRange = 0xFFFFFF00u;
+constexpr uint32_t kNoLoad = 0xFFFFFFF0u;
+// dword 3 of the resource: 32-bit data format, raw (untyped) access
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ inline rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ inline float buf_load1(rsrc_t r, uint32_t off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline double buf_load1(rsrc_t r, uint32_t off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline f32x4 buf_load4(rsrc_t r, uint32_t off, float) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ inline f64x4 buf_load4(rsrc_t r, uint32_t off, double) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 lo = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const d2 hi = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off == kNoLoad ? kNoLoad : off + 16, 0, 0));
+    return f64x4{lo[0], lo[1], hi[0], hi[1]};
+}
+
+// a / b and a % b for non-negative 64-bit values, in 32-bit arithmetic when
+// both fit (the common case, and far cheaper on the GPU).
+__device__ inline int64_t div64(int64_t a, int64_t b) {
+    if (((a | b) >> 31) == 0) return (int64_t)((uint32_t)a / (uint32_t)b);
+    return a / b;
+}
+__device__ inline int64_t mod64(int64_t a, int64_t b) {
+    if (((a | b) >> 31) == 0) return (int64_t)((uint32_t)a % (uint32_t)b);
+    return a % b;
+}
+
+// Two-phase tile form of the row builder for the MTTKRP kernels: rows
+// [row0, row0 + NROWS) of K, columns [coff, coff + RP).  Thread t owns
+// column t % RP and RUN = NROWS * RP / 256 consecutive rows.  fetch() issues
+// every global load of the thread's run into registers and returns without
+// waiting; put() multiplies and stores.  Kernels call fetch() for the next
+// tile, then issue their own loads and multiply the current tile, and call
+// put() afterwards, so the factor loads overlap the matrix work instead of
+// stalling it.  When RUN does not exceed the fastest factor's row count the
+// fastest index wraps at most once in a run: the run needs RUN rows of the
+// fastest factor and the slow partial Hadamard products (Algorithm 1's
+// stored products) at most at two multi-indices, whose first ZS factor
+// values are prefetched too.  Otherwise put() falls back to build_krp_rows.
+template <typename T, int RP, int NROWS>
+struct KrpTile {
+    static constexpr int RUN = NROWS * RP / kThreads;
+    static constexpr int ZS = 4;
+    static_assert(RUN >= 1 && RUN * kThreads == NROWS * RP, "tile must split evenly over the block");
+    T u[RUN];
+    T f0[ZS], f1[ZS];
+    int64_t g0, first_wrap;
+    bool fast;
+
+    __device__ inline void fetch(const Krp<T> &k, int R, int coff, int64_t row0, int64_t row_limit) {
+        const int t = threadIdx.x;
+        const int c = coff + t % RP;
+        const int64_t lim = min(row_limit, k.rows);
+        const bool col_ok = c < R;
+        g0 = row0 + (t / RP) * RUN;
+        fast = k.Z > 0 && k.J[0] >= RUN;
+        first_wrap = RUN;
+        if (!fast) return;
+        const int64_t J0 = k.J[0];
+        const int64_t i0 = mod64(g0, J0);
+        first_wrap = J0 - i0;
+        const T *__restrict__ U0 = k.U[0];
+#pragma unroll
+        for (int q = 0; q < RUN; ++q) {
+            int64_t idx = i0 + q;
+            if (idx >= J0) idx -= J0;
+            u[q] = (col_ok && g0 + q < lim) ? U0[idx * R + c] : T(0);
+        }
+        const int64_t g1 = g0 + first_wrap;
+        const bool ok0 = col_ok && g0 < lim;
+        const bool ok1 = col_ok && first_wrap < RUN && g1 < lim;
+#pragma unroll
+        for (int z = 0; z < ZS; ++z) {
+            const int zz = z + 1;
+            f0[z] = T(1);
+            f1[z] = T(1);
+            if (zz < k.Z) {
+                if (ok0) f0[z] = k.U[zz][mod64(div64(g0, k.stride[zz]), k.J[zz]) * R + c];
+                if (ok1) f1[z] = k.U[zz][mod64(div64(g1, k.stride[zz]), k.J[zz]) * R + c];
+            }
+        }
+    }
+
+    template <typename Store>
+    __device__ inline void put(const Krp<T> &k, int R, int coff, int64_t row0, int64_t row_limit, Store store) {
+        const int t = threadIdx.x;
+        const int cl = t % RP;
+        const int c = coff + cl;
+        const int q0 = (t / RP) * RUN;
+        const int64_t lim = min(row_limit, k.rows);
+        const bool col_ok = c < R;
+        if (k.Z == 0) {
+#pragma unroll
+            for (int q = 0; q < RUN; ++q) store(q0 + q, cl, (col_ok && row0 + q0 + q < lim) ? T(1) : T(0));
+            return;
+        }
+        if (!fast) {
+            build_krp_rows<T>(k, R, coff, RP, row0, NROWS, row_limit, store);
+            return;
+        }
+        T s0 = (f0[0] * f0[1]) * (f0[2] * f0[3]);
+        T s1 = (f1[0] * f1[1]) * (f1[2] * f1[3]);
+        const int64_t g1 = g0 + first_wrap;
+        for (int zz = ZS + 1; zz < k.Z; ++zz) {  // only for products of more than 5 factors
+            if (col_ok && g0 < lim) s0 *= k.U[zz][mod64(div64(g0, k.stride[zz]), k.J[zz]) * R + c];
+            if (col_ok && first_wrap < RUN && g1 < lim)
+                s1 *= k.U[zz][mod64(div64(g1, k.stride[zz]), k.J[zz]) * R + c];
+        }
+#pragma unroll
+        for (int q = 0; q < RUN; ++q) store(q0 + q, cl, (q < first_wrap ? s0 : s1) * u[q]);
+    }
+};
+
+// Raw factor values of one row of a Khatri-Rao product for NB lane columns,
+// fetched ahead of use (first ZS factors) and multiplied when needed.  The
+// row index is the same in every lane, so the index arithmetic is scalar;
+// the loads are unconditional buffer loads (a column past R reads zero).
+template <typename T, int NB>
+struct KrpRowVals {
+    static constexpr int ZS = 4;
+    T f[NB][ZS];
+    int64_t g;
+
+    __device__ inline void fetch(const Krp<T> &k, int R, int cbase, int64_t row) {
+        g = row;
+#pragma unroll
+        for (int z = 0; z < ZS; ++z) {
+            const int zz = z < k.Z ? z : 0;  // k.Z >= 1 whenever this is used
+            const rsrc_t rs = make_rsrc(k.U[zz], (uint32_t)(k.J[zz] * R * (int64_t)sizeof(T)));
+            const int64_t rowz = mod64(div64(row, k.stride[zz]), k.J[zz]);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int c = cbase + 16 * nb;
+                const uint32_t off = (c < R) ? (uint32_t)((rowz * R + c) * (int64_t)sizeof(T)) : kNoLoad;
+                const T v = buf_load1(rs, off, T(0));
+                f[nb][z] = (z < k.Z) ? v : T(1);
+            }
+        }
+    }
+    __device__ inline T value(const Krp<T> &k, int R, int cbase, int nb) const {
+        const int c = cbase + 16 * nb;
+        if (c >= R) return T(0);
+        T v = (f[nb][0] * f[nb][1]) * (f[nb][2] * f[nb][3]);
+        for (int z = ZS; z < k.Z; ++z) v *= k.U[z][mod64(div64(g, k.stride[z]), k.J[z]) * R + c];
+        return v;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // MFMA wrappers.  16x16x4 (f32, f64): lane l holds A[l%16][l/16] and
 // B[l/16][l%16].  Accumulator element j (0..3) of lane l holds
 // D[acc_row<T>(l, j)][l%16]: row 4*(l/16)+j for f32 but 4*j+l/16 for f64

@@ -32,19 +32,55 @@
 namespace cpm {
 
 // ---------------------------------------------------------------------------
-// Left-first contraction.
-//   grid.x = row tile, grid.y = split s (contiguous range of work units; a
-//            unit is one l-chunk of one slab, units ordered slab-major),
-//   grid.z = column block (16*NB columns starting at c0 = z*16*NB).
-//   The 4 waves are arranged WI (row groups of 16*MB rows) x WL (waves that
-//   share rows and interleave the 16-wide l-steps of each chunk).
+// Shared structure of both contraction kernels.
+//
+// The contracted Khatri-Rao product of each kernel is split into an inner
+// part over the fastest modes of that side and an outer part over the rest:
+// K(g_in + G_in * o, c) = K_in(g_in, c) * S(o, c).  (For K_L this is
+// Algorithm 1's observation that the partial Hadamard product of the slow
+// factors stays fixed while the fast indices run.)  A work-group keeps one
+// tile of K_in -- a fixed chunk of its rows, for a fixed block of rank
+// columns -- in LDS for its whole life, and streams X block by block over
+// the outer index o: each block is contracted against the tile on MFMA, and
+// at the block's end the block result is scaled by S(o, :) and added to the
+// running total.  That scaling is the multi-TTV of the 2-step scheme; for
+// the left-first kernel it carries both the slow left modes and every right
+// mode.  No tile is rebuilt and no barrier is taken inside the stream.
+//
+// Each wave streams "steps" of 16 contracted indices (4 MFMA k-steps of 4)
+// and keeps two steps of X in flight in registers ahead of the one it
+// multiplies (a ring of three register sets used in rotation).
+// ---------------------------------------------------------------------------
+
+// Per-block scale S(o, c) for the lane's NB columns: the factor values of
+// the block after the current one are loaded at the current block's end and
+// multiplied only when that block ends, so the loads never stall the stream.
+template <typename T, int NB>
+struct BlockScale {
+    KrpRowVals<T, NB> next;
+    __device__ inline void prefetch(const Krp<T> &k, int R, int cbase, int64_t o) { next.fetch(k, R, cbase, o); }
+    __device__ inline T value(const Krp<T> &k, int R, int cbase, int nb) const {
+        return next.value(k, R, cbase, nb);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Left-first contraction (internal and last modes).
+// X is viewed as X[r][i][h][l_in]: l_in over the inner left modes (IL_in
+// entries, contiguous), h over the outer left modes, i = i_n, r over the
+// right modes; row (i, h, r) starts at l_in = 0 and rows of consecutive i
+// are IL = IL_in * IL_out apart.  The outer block o = h + IL_out * r.
+//   grid.x = row tile of 16*MB rows of i
+//   grid.y = lc + nlc * s: inner chunk lc of LC = 64*SPB entries of l_in,
+//            split s = a contiguous range of blocks_per_split outer blocks
+//   grid.z = column block (16*NB columns from c0 = z*16*NB)
+// Wave w owns entries [w*16*SPB, (w+1)*16*SPB) of the chunk for all rows.
 // partial: [gridDim.y][In][R].
 // ---------------------------------------------------------------------------
 template <typename T, int NB, int MB, bool V4>
 __global__ __launch_bounds__(kThreads) void k_contract_left(
-    const T *__restrict__ X, int64_t IL, int64_t In, int64_t IR, Krp<T> kl, Krp<T> kr, int R,
-    int LC, int WI, int64_t nlc, int64_t units_per_split, int64_t total_units,
-    T *__restrict__ partial) {
+    const T *__restrict__ X, int64_t IL_in, int64_t IL_out, int64_t In, int64_t n_outer, Krp<T> kin,
+    Krp<T> kout, int R, int SPB, int64_t nlc, int64_t blocks_per_split, T *__restrict__ partial) {
     typedef typename Vec4<T>::type acc_t;
     constexpr int RP = NB * 16;
     constexpr int PITCH = RP + 4;
@@ -53,15 +89,21 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, kg = lane >> 4;
-    const int WL = 4 / WI;
-    const int wi = wave % WI, wl = wave / WI;
     const int c0 = blockIdx.z * RP;
-    const int64_t TI = (int64_t)WI * 16 * MB;
-    const int64_t row_base = (int64_t)blockIdx.x * TI + (int64_t)wi * 16 * MB;
-    const int64_t u_begin = (int64_t)blockIdx.y * units_per_split;
-    const int64_t u_end = min(total_units, u_begin + units_per_split);
-    const bool single_chunk = (nlc == 1);
-    const int tile_elems = LC * PITCH;
+    const int LC = 64 * SPB;
+    const int64_t lc = blockIdx.y % nlc;
+    const int64_t split = blockIdx.y / nlc;
+    const int64_t l0 = lc * LC;                       // first inner entry of the chunk
+    const int64_t lend = min(IL_in, l0 + LC);         // one past the last
+    const int64_t IL = IL_in * IL_out;
+    const int64_t row_base = (int64_t)blockIdx.x * 16 * MB;
+    const int64_t o_begin = split * blocks_per_split;
+    const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
+    const bool has_out = kout.Z > 0;
+
+    // The chunk of K_in for this work-group, built once (rows past IL_in and
+    // columns past R are zero).
+    build_krp_rows<T>(kin, R, c0, RP, l0, LC, IL_in, [&](int q, int c, T v) { tile[q * PITCH + c] = v; });
 
     acc_t acc[MB][NB], tot[MB][NB];
 #pragma unroll
@@ -71,94 +113,126 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
             acc[mb][nb] = acc_t{0, 0, 0, 0};
             tot[mb][nb] = acc_t{0, 0, 0, 0};
         }
+    int64_t rowoff[MB];
+    bool rok[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const int64_t row = row_base + 16 * mb + m;
+        rok[mb] = row < In;
+        rowoff[mb] = (rok[mb] ? row : 0) * IL;
+    }
+    const int64_t lane_l = l0 + wave * 16 * SPB + 4 * kg;  // this lane's entries within a block: + 16*s + e
 
-    auto build = [&](int64_t u, int buf) {
-        const int64_t l0 = (u % nlc) * (int64_t)LC;
-        T *dst = tile + buf * tile_elems;
-        build_krp_rows<T>(kl, R, c0, RP, l0, LC, IL, [&](int q, int c, T v) {
-            dst[q * PITCH + c] = v;
-        });
+    auto block_base = [&](int64_t o) -> const T * {
+        const int64_t r = o / IL_out, h = o - r * IL_out;
+        return X + r * In * IL + h * IL_in;
     };
 
-    if (u_begin < u_end) build(u_begin, 0);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t u = u_begin; u < u_end; ++u) {
-        const int64_t r = u / nlc, lc = u % nlc;
-        if (!single_chunk && u + 1 < u_end) build(u + 1, buf ^ 1);
-        const T *K = tile + buf * tile_elems;
-        const int64_t l0 = lc * (int64_t)LC;
-        const int64_t lend = min(IL, l0 + (int64_t)LC);
-        const int nsteps = (int)((lend - l0 + 15) / 16);
-        const T *xr[MB];
-        bool rok[MB];
+    // load cursor
+    int64_t lo = o_begin;
+    int ls = 0;
+    // X loads: one buffer resource per m-block, based at the m-block's first
+    // row in the current block, so lane offsets are (m * IL + l) entries;
+    // rows past In, entries past the chunk and blocks past the split get
+    // kNoLoad and read zeros.  No load sits behind a branch, which lets the
+    // compiler wait for exactly the step being multiplied.
+    rsrc_t rs[MB];
+    auto set_block = [&](int64_t o) {
+        const T *b = block_base(o);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) rs[mb] = make_rsrc(b + (row_base + 16 * mb) * IL, kRsrcRange);
+    };
+    if (o_begin < o_end) set_block(o_begin);
+    const uint32_t lane_row = (uint32_t)(m * IL);
+    auto load_step = [&](T (&a)[MB][4]) {
+        const int64_t l = lane_l + 16 * ls;
+        const bool live = lo < o_end;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-            const int64_t row = row_base + 16 * mb + m;
-            rok[mb] = row < In;
-            xr[mb] = X + ((r * In + (rok[mb] ? row : 0)) * IL);
-        }
-        for (int st = wl; st < nsteps; st += WL) {
-            const int64_t lb = l0 + (int64_t)st * 16 + 4 * kg;
-            T a[MB][4];
+            if (V4) {
+                const bool ok = live && rok[mb] && l < lend;
+                const uint32_t off = ok ? (uint32_t)((lane_row + l) * sizeof(T)) : kNoLoad;
+                const acc_t v = buf_load4(rs[mb], off, T(0));
+                a[mb][0] = v[0]; a[mb][1] = v[1]; a[mb][2] = v[2]; a[mb][3] = v[3];
+            } else {
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                if (V4) {
-                    if (rok[mb] && lb < lend) {
-                        const acc_t v = *reinterpret_cast<const acc_t *>(xr[mb] + lb);
-                        a[mb][0] = v[0]; a[mb][1] = v[1]; a[mb][2] = v[2]; a[mb][3] = v[3];
-                    } else {
-                        a[mb][0] = a[mb][1] = a[mb][2] = a[mb][3] = T(0);
+                for (int e = 0; e < 4; ++e) {
+                    const bool ok = live && rok[mb] && l + e < lend;
+                    const uint32_t off = ok ? (uint32_t)((lane_row + l + e) * sizeof(T)) : kNoLoad;
+                    a[mb][e] = buf_load1(rs[mb], off, T(0));
+                }
+            }
+        }
+        if (++ls == SPB) {
+            ls = 0;
+            ++lo;
+            if (lo < o_end) set_block(lo);
+        }
+    };
+
+    // compute cursor
+    int64_t co = o_begin;
+    int cs = 0;
+    BlockScale<T, NB> sc;
+    if (has_out && o_begin < o_end) sc.prefetch(kout, R, c0 + m, o_begin);
+    __syncthreads();  // tile ready
+    auto compute_step = [&](const T (&a)[MB][4]) {
+        const T *kb = tile + (wave * 16 * SPB + 16 * cs + 4 * kg) * PITCH + m;
+        T b[4][NB];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) b[t][nb] = kb[t * PITCH + 16 * nb];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma4(a[mb][t], b[t][nb], acc[mb][nb]);
+        if (++cs == SPB) {
+            cs = 0;
+            if (has_out) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const T s = sc.value(kout, R, c0 + m, nb);
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb) {
+                        tot[mb][nb] += acc[mb][nb] * s;
+                        acc[mb][nb] = acc_t{0, 0, 0, 0};
                     }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        a[mb][e] = (rok[mb] && lb + e < lend) ? xr[mb][lb + e] : T(0);
                 }
+                if (co + 1 < o_end) sc.prefetch(kout, R, c0 + m, co + 1);
             }
-            const int qb = st * 16 + 4 * kg;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                T b[NB];
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) b[nb] = K[(qb + t) * PITCH + 16 * nb + m];
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-                        acc[mb][nb] = mfma4(a[mb][t], b[nb], acc[mb][nb]);
-            }
+            ++co;
         }
-        const bool slab_end = (lc == nlc - 1) || (u + 1 == u_end);
-        // (a right product exists whenever mode n is not the last mode, even
-        // if every mode to the right has size 1)
-        if (kr.Z > 0 && slab_end) {
-            // multi-TTV with the right Khatri-Rao product: scale this slab's
-            // partial MTTKRP by K_R(r, c) for the lane's columns.
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int c = c0 + 16 * nb + m;
-                const T kv = (c < R) ? krp_value(kr, R, r, c) : T(0);
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    tot[mb][nb] += acc[mb][nb] * kv;
-                    acc[mb][nb] = acc_t{0, 0, 0, 0};
-                }
-            }
-        }
-        if (!single_chunk) {
-            __syncthreads();
-            buf ^= 1;
-        }
+    };
+
+    T xa[MB][4], xb[MB][4], xc[MB][4];
+    const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
+    load_step(xa);
+    load_step(xb);
+    int64_t st = 0;
+    for (; st + 3 <= nsteps; st += 3) {
+        load_step(xc);
+        compute_step(xa);
+        load_step(xa);
+        compute_step(xb);
+        load_step(xb);
+        compute_step(xc);
     }
-    if (kr.Z == 0) {
+    if (st < nsteps) {
+        compute_step(xa);
+        ++st;
+    }
+    if (st < nsteps) compute_step(xb);
+    if (!has_out) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) tot[mb][nb] = acc[mb][nb];
     }
 
-    // Sum the WL waves that share rows, in wave order, and store the partial.
+    // Sum the 4 waves (which share rows) in wave order and store the partial.
     __syncthreads();
     T *red = tile;  // [wave][mb][nb][j][lane]
 #pragma unroll
@@ -169,117 +243,186 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
             for (int j = 0; j < 4; ++j)
                 red[(((wave * MB + mb) * NB + nb) * 4 + j) * 64 + lane] = tot[mb][nb][j];
     __syncthreads();
-    const int per_wi = MB * NB * 4 * 64;
-    for (int e = tid; e < WI * per_wi; e += kThreads) {
-        const int wi2 = e / per_wi, rem = e % per_wi;
-        const int ln = rem & 63, j = (rem >> 6) & 3, blk = rem >> 8;
+    constexpr int PER_WAVE = MB * NB * 4 * 64;
+    for (int e = tid; e < PER_WAVE; e += kThreads) {
+        const int ln = e & 63, j = (e >> 6) & 3, blk = e >> 8;
         const int nb = blk % NB, mb = blk / NB;
-        T s = T(0);
-        for (int w2 = 0; w2 < WL; ++w2) {
-            const int wave2 = w2 * WI + wi2;
-            s += red[(((wave2 * MB + mb) * NB + nb) * 4 + j) * 64 + ln];
-        }
-        const int64_t row = (int64_t)blockIdx.x * TI + (int64_t)wi2 * 16 * MB + 16 * mb + acc_row<T>(ln, j);
+        const T sum = ((red[e] + red[PER_WAVE + e]) + red[2 * PER_WAVE + e]) + red[3 * PER_WAVE + e];
+        const int64_t row = row_base + 16 * mb + acc_row<T>(ln, j);
         const int c = c0 + 16 * nb + (ln & 15);
-        if (row < In && c < R) partial[((int64_t)blockIdx.y * In + row) * R + c] = s;
+        if (row < In && c < R) partial[((int64_t)blockIdx.y * In + row) * R + c] = sum;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Right-first contraction over the slow index r of X viewed as [IR][J].
-//   grid.x = tile of 64*MJ entries of J, grid.y = split s (rows
-//   [s*rows_per_split, ...)), grid.z = rank-column block.  The 4 waves interleave
-//   the 4-row k-steps of each chunk of RC rows of K_R.
-// Lane (m, kg) loads 4 consecutive j at 4m + 64g; component e feeds m-block
-// 4g + e, so output row j = jt0 + 64g + 4*m' + e for accumulator row m'.
+// Right-first contraction (mode 0, and internal modes with a short left
+// product): X viewed as X[o][r_in][j] with j over J = In*IL contiguous
+// entries, r_in over the inner right modes (IR_in), o over the outer right
+// modes.  T(j, c) = sum_o S(o, c) sum_{r_in} X[o][r_in][j] K_in(r_in, c).
+//   grid.x = j-tile of 64*MJ entries
+//   grid.y = lc + nlc * s: inner chunk lc of LC = 64*SPB rows of r_in and
+//            split s of the outer blocks
+//   grid.z = rank-column block
+// Wave w owns rows [w*16*SPB, (w+1)*16*SPB) of the chunk; within a step of
+// 16 rows, k-step t uses rows 4*kg + t, so lane (m, kg) loads 4 consecutive
+// j at 4m + 64g from each of its 4 rows, and component e feeds m-block
+// 4g + e (accumulator row m' of that block is j = jt0 + 64g + 4m' + e).
 // partial: [gridDim.y][J][R].
 // ---------------------------------------------------------------------------
 template <typename T, int NB, int MJ, bool V4>
 __global__ __launch_bounds__(kThreads) void k_contract_right(
-    const T *__restrict__ X, int64_t J, int64_t IR, Krp<T> kr, int R, int RC,
-    int64_t rows_per_split, T *__restrict__ partial) {
+    const T *__restrict__ X, int64_t J, int64_t IR_in, int64_t n_outer, Krp<T> kin, Krp<T> kout, int R,
+    int SPB, int64_t nlc, int64_t blocks_per_split, T *__restrict__ partial) {
     typedef typename Vec4<T>::type acc_t;
     constexpr int RP = NB * 16;
-    constexpr int PITCH = RP + 16;
+    constexpr int PITCH = RP + 4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, kg = lane >> 4;
     const int c0 = blockIdx.z * RP;
+    const int LC = 64 * SPB;
+    const int64_t lc = blockIdx.y % nlc;
+    const int64_t split = blockIdx.y / nlc;
+    const int64_t r0 = lc * LC;
+    const int64_t rend = min(IR_in, r0 + LC);
     const int64_t jt0 = (int64_t)blockIdx.x * 64 * MJ;
-    const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
-    const int64_t r_end = min(IR, r_begin + rows_per_split);
-    const int tile_elems = RC * PITCH;
+    const int64_t o_begin = split * blocks_per_split;
+    const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
+    const bool has_out = kout.Z > 0;
 
-    acc_t acc[MJ][4][NB];
+    build_krp_rows<T>(kin, R, c0, RP, r0, LC, IR_in, [&](int q, int c, T v) { tile[q * PITCH + c] = v; });
+
+    acc_t acc[MJ][4][NB], tot[MJ][4][NB];
 #pragma unroll
     for (int g = 0; g < MJ; ++g)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[g][e][nb] = acc_t{0, 0, 0, 0};
-
-    auto build = [&](int64_t rc0, int buf) {
-        T *dst = tile + buf * tile_elems;
-        build_krp_rows<T>(kr, R, c0, RP, rc0, RC, r_end, [&](int q, int c, T v) {
-            dst[q * PITCH + c] = v;
-        });
-    };
-
+            for (int nb = 0; nb < NB; ++nb) {
+                acc[g][e][nb] = acc_t{0, 0, 0, 0};
+                tot[g][e][nb] = acc_t{0, 0, 0, 0};
+            }
+    int64_t jj[MJ];
     bool jok[MJ];
-    const T *xc[MJ];
 #pragma unroll
     for (int g = 0; g < MJ; ++g) {
-        const int64_t j = jt0 + 64 * g + 4 * m;
-        jok[g] = j < J;
-        xc[g] = X + (jok[g] ? j : 0);
+        jj[g] = jt0 + 64 * g + 4 * m;
+        jok[g] = jj[g] < J;
     }
 
-    if (r_begin < r_end) build(r_begin, 0);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t rc0 = r_begin; rc0 < r_end; rc0 += RC) {
-        if (rc0 + RC < r_end) build(rc0 + RC, buf ^ 1);
-        const T *K = tile + buf * tile_elems;
-        const int nsteps = (int)((min((int64_t)RC, r_end - rc0) + 3) / 4);
-        for (int st = wave; st < nsteps; st += 4) {
-            const int64_t rk = rc0 + (int64_t)st * 4 + kg;
-            const bool rrow = rk < r_end;
-            T a[MJ][4];
+    // X loads: one buffer resource per block for this wave's rows, based at
+    // (row r0 + w*16*SPB, column jt0), so lane offsets are
+    // ((16*ls + 4*kg + t) * J + 64*g + 4*m) entries; rows past the chunk,
+    // columns past J and blocks past the split read zeros.
+    int64_t lo = o_begin;
+    int ls = 0;
+    const int64_t wrow = r0 + wave * 16 * SPB;
+    auto wave_base = [&](int64_t o) { return X + (o * IR_in + wrow) * J + jt0; };
+    rsrc_t rs = make_rsrc(wave_base(o_begin < o_end ? o_begin : 0), kRsrcRange);
+    auto load_step = [&](T (&a)[4][MJ][4]) {
+        const bool live = lo < o_end;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t rl = 16 * ls + 4 * kg + t;  // row within this wave's rows
+            const bool rok = live && wrow + rl < rend;
 #pragma unroll
             for (int g = 0; g < MJ; ++g) {
-                const T *p = xc[g] + rk * J;
+                const int64_t jl = 64 * g + 4 * m;  // column within the tile
                 if (V4) {
-                    if (rrow && jok[g]) {
-                        const acc_t v = *reinterpret_cast<const acc_t *>(p);
-                        a[g][0] = v[0]; a[g][1] = v[1]; a[g][2] = v[2]; a[g][3] = v[3];
-                    } else {
-                        a[g][0] = a[g][1] = a[g][2] = a[g][3] = T(0);
-                    }
+                    const bool ok = rok && jok[g];
+                    const uint32_t off = ok ? (uint32_t)((rl * J + jl) * sizeof(T)) : kNoLoad;
+                    const acc_t v = buf_load4(rs, off, T(0));
+                    a[t][g][0] = v[0]; a[t][g][1] = v[1]; a[t][g][2] = v[2]; a[t][g][3] = v[3];
                 } else {
-                    const int64_t j = jt0 + 64 * g + 4 * m;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) a[g][e] = (rrow && j + e < J) ? p[e] : T(0);
+                    for (int e = 0; e < 4; ++e) {
+                        const bool ok = rok && jj[g] + e < J;
+                        const uint32_t off = ok ? (uint32_t)((rl * J + jl + e) * sizeof(T)) : kNoLoad;
+                        a[t][g][e] = buf_load1(rs, off, T(0));
+                    }
                 }
             }
-            T b[NB];
+        }
+        if (++ls == SPB) {
+            ls = 0;
+            ++lo;
+            if (lo < o_end) rs = make_rsrc(wave_base(lo), kRsrcRange);
+        }
+    };
+
+    int64_t co = o_begin;
+    int cs = 0;
+    BlockScale<T, NB> sc;
+    if (has_out && o_begin < o_end) sc.prefetch(kout, R, c0 + m, o_begin);
+    __syncthreads();
+    auto compute_step = [&](const T (&a)[4][MJ][4]) {
+        const T *kb = tile + (wave * 16 * SPB + 16 * cs + 4 * kg) * PITCH + m;
+        T b[4][NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) b[nb] = K[(st * 4 + kg) * PITCH + 16 * nb + m];
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) b[t][nb] = kb[t * PITCH + 16 * nb];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int g = 0; g < MJ; ++g)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) acc[g][e][nb] = mfma4(a[g][e], b[nb], acc[g][e][nb]);
+                    for (int nb = 0; nb < NB; ++nb) acc[g][e][nb] = mfma4(a[t][g][e], b[t][nb], acc[g][e][nb]);
+        if (++cs == SPB) {
+            cs = 0;
+            if (has_out) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const T s = sc.value(kout, R, c0 + m, nb);
+#pragma unroll
+                    for (int g = 0; g < MJ; ++g)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            tot[g][e][nb] += acc[g][e][nb] * s;
+                            acc[g][e][nb] = acc_t{0, 0, 0, 0};
+                        }
+                }
+                if (co + 1 < o_end) sc.prefetch(kout, R, c0 + m, co + 1);
+            }
+            ++co;
         }
-        __syncthreads();
-        buf ^= 1;
+    };
+
+    T xa[4][MJ][4], xb[4][MJ][4], xc[4][MJ][4];
+    const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
+    load_step(xa);
+    load_step(xb);
+    int64_t st = 0;
+    for (; st + 3 <= nsteps; st += 3) {
+        load_step(xc);
+        compute_step(xa);
+        load_step(xa);
+        compute_step(xb);
+        load_step(xb);
+        compute_step(xc);
+    }
+    if (st < nsteps) {
+        compute_step(xa);
+        ++st;
+    }
+    if (st < nsteps) compute_step(xb);
+    if (!has_out) {
+#pragma unroll
+        for (int g = 0; g < MJ; ++g)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) tot[g][e][nb] = acc[g][e][nb];
     }
 
-    // Sum the 4 waves in order and store the partial.
+    // Sum the 4 waves in wave order and store the partial.
+    __syncthreads();
+    constexpr int PER_WAVE = MJ * 4 * NB * 4 * 64;
     T *red = tile;  // [wave][g][e][nb][jj][lane]
-    const int per_wave = MJ * 4 * NB * 4 * 64;
 #pragma unroll
     for (int g = 0; g < MJ; ++g)
 #pragma unroll
@@ -287,16 +430,16 @@ __global__ __launch_bounds__(kThreads) void k_contract_right(
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-                    red[wave * per_wave + (((g * 4 + e) * NB + nb) * 4 + jj) * 64 + lane] = acc[g][e][nb][jj];
+                for (int q = 0; q < 4; ++q)
+                    red[wave * PER_WAVE + (((g * 4 + e) * NB + nb) * 4 + q) * 64 + lane] = tot[g][e][nb][q];
     __syncthreads();
-    for (int q = tid; q < per_wave; q += kThreads) {
-        const int ln = q & 63, jj = (q >> 6) & 3, blk = q >> 8;
+    for (int q = tid; q < PER_WAVE; q += kThreads) {
+        const int ln = q & 63, qq = (q >> 6) & 3, blk = q >> 8;
         const int nb = blk % NB, ge = blk / NB, e = ge % 4, g = ge / 4;
-        T s = red[q] + red[per_wave + q] + red[2 * per_wave + q] + red[3 * per_wave + q];
-        const int64_t j = jt0 + 64 * g + 4 * acc_row<T>(ln, jj) + e;
+        const T sum = ((red[q] + red[PER_WAVE + q]) + red[2 * PER_WAVE + q]) + red[3 * PER_WAVE + q];
+        const int64_t j = jt0 + 64 * g + 4 * acc_row<T>(ln, qq) + e;
         const int c = c0 + 16 * nb + (ln & 15);
-        if (j < J && c < R) partial[((int64_t)blockIdx.y * J + j) * R + c] = s;
+        if (j < J && c < R) partial[((int64_t)blockIdx.y * J + j) * R + c] = sum;
     }
 }
 
