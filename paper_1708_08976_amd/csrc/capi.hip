@@ -82,7 +82,8 @@ struct Plan {
     int p;                    // left: inner modes [0, p); right: inner modes [mode+1, p)
     int64_t G_in, G_out;      // inner rows of the contracted product; left: outer left extent
     int64_t n_outer;          // outer blocks
-    int SPB, LC;              // steps per block per wave, inner chunk (64 * SPB)
+    int SPB, LC;              // steps per block per wave, inner chunk
+    int Q;                    // left: 16-entry groups per row per step
     int64_t nlc, bps, S;      // inner chunks, blocks per split, splits
     int64_t ntiles;           // row tiles (left) / j tiles (right)
     bool v4;
@@ -117,7 +118,10 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
     }
     const bool left = p.IL >= 16;
     const bool dbl = dt == CPM_F64;
-    const int nbmax = dbl ? 2 : 8;
+    // n-blocks (16 rank columns) per work-group; wider ranks take several
+    // column blocks.  The right-first kernel keeps four accumulator rows per
+    // lane, so it stays at two blocks.
+    const int nbmax = left ? (dbl ? 2 : 8) : (dbl ? 1 : 2);
     int nb = RPtot / 16;
     if (nb <= nbmax) {
         p.NB = pow2_at_least(nb);
@@ -141,13 +145,15 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
     };
     if (left) {
         p.kind = kLeft;
-        p.MB = dbl ? 2 : std::min(4, std::max(1, 16 / p.NB));
+        p.MB = (p.NB >= 8 || (dbl && p.NB >= 2)) ? 1 : 2;
         while (p.MB > 1 && 16 * p.MB / 2 >= p.In) p.MB /= 2;
         p.p = pick_inner(0, mode, p.G_in);
         p.G_out = p.IL / p.G_in;
         p.n_outer = p.G_out * p.IR;
-        p.LC = (int)std::min<int64_t>(lcmax, ceil_div(p.G_in, 64) * 64);
-        p.SPB = p.LC / 64;
+        p.Q = (p.G_in > 64) ? 2 : 1;  // 128-byte row bursts once rows are long enough
+        const int64_t unit = 64 * p.Q;
+        p.LC = (int)std::min<int64_t>(lcmax / unit * unit, ceil_div(p.G_in, unit) * unit);
+        p.SPB = p.LC / (int)unit;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.In, 16 * p.MB);
         const size_t red = (size_t)4 * p.MB * p.NB * 256 * sz;
@@ -186,26 +192,30 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
 }
 
 // ----------------------------- kernel dispatch -----------------------------
-template <typename T, int NB, int MB>
+template <typename T, int NB, int MB, int Q>
 void launch_left_t(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kout, int R, T *partial,
                    hipStream_t st) {
     dim3 grid((unsigned)p.ntiles, (unsigned)(p.S * p.nlc), (unsigned)p.ncb);
     if (p.v4)
-        hipLaunchKernelGGL((k_contract_left<T, NB, MB, true>), grid, dim3(kThreads), p.lds, st, X, p.G_in, p.G_out,
-                           p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+        hipLaunchKernelGGL((k_contract_left<T, NB, MB, true, Q>), grid, dim3(kThreads), p.lds, st, X, p.G_in,
+                           p.G_out, p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
     else
-        hipLaunchKernelGGL((k_contract_left<T, NB, MB, false>), grid, dim3(kThreads), p.lds, st, X, p.G_in, p.G_out,
-                           p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+        hipLaunchKernelGGL((k_contract_left<T, NB, MB, false, Q>), grid, dim3(kThreads), p.lds, st, X, p.G_in,
+                           p.G_out, p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+}
+
+template <typename T, int NB, int MB>
+void launch_left_q(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kout, int R, T *partial,
+                   hipStream_t st) {
+    if (p.Q == 2) launch_left_t<T, NB, MB, 2>(p, X, kin, kout, R, partial, st);
+    else launch_left_t<T, NB, MB, 1>(p, X, kin, kout, R, partial, st);
 }
 
 template <typename T, int NB>
 void launch_left_m(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kout, int R, T *partial,
                    hipStream_t st) {
-    switch (p.MB) {
-    case 1: launch_left_t<T, NB, 1>(p, X, kin, kout, R, partial, st); break;
-    case 2: launch_left_t<T, NB, 2>(p, X, kin, kout, R, partial, st); break;
-    default: launch_left_t<T, NB, 4>(p, X, kin, kout, R, partial, st); break;
-    }
+    if (p.MB == 2) launch_left_q<T, NB, 2>(p, X, kin, kout, R, partial, st);
+    else launch_left_q<T, NB, 1>(p, X, kin, kout, R, partial, st);
 }
 
 template <typename T>
@@ -218,20 +228,14 @@ void launch_left<float>(const Plan &p, const float *X, const Krp<float> &kin, co
     case 1: launch_left_m<float, 1>(p, X, kin, kout, R, partial, st); break;
     case 2: launch_left_m<float, 2>(p, X, kin, kout, R, partial, st); break;
     case 4: launch_left_m<float, 4>(p, X, kin, kout, R, partial, st); break;
-    default: launch_left_m<float, 8>(p, X, kin, kout, R, partial, st); break;
+    default: launch_left_q<float, 8, 1>(p, X, kin, kout, R, partial, st); break;
     }
 }
 template <>
 void launch_left<double>(const Plan &p, const double *X, const Krp<double> &kin, const Krp<double> &kout, int R,
                          double *partial, hipStream_t st) {
-    // float64: MB <= 2, NB <= 2
-    if (p.NB == 1) {
-        if (p.MB == 1) launch_left_t<double, 1, 1>(p, X, kin, kout, R, partial, st);
-        else launch_left_t<double, 1, 2>(p, X, kin, kout, R, partial, st);
-    } else {
-        if (p.MB == 1) launch_left_t<double, 2, 1>(p, X, kin, kout, R, partial, st);
-        else launch_left_t<double, 2, 2>(p, X, kin, kout, R, partial, st);
-    }
+    if (p.NB == 1) launch_left_m<double, 1>(p, X, kin, kout, R, partial, st);
+    else launch_left_q<double, 2, 1>(p, X, kin, kout, R, partial, st);
 }
 
 template <typename T, int NB, int MJ>
@@ -252,21 +256,18 @@ void launch_right(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &ko
 template <>
 void launch_right<float>(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
                          float *partial, hipStream_t st) {
-    switch (p.NB) {
-    case 1:
+    if (p.NB == 1) {
         if (p.MB == 2) launch_right_t<float, 1, 2>(p, X, kin, kout, R, partial, st);
         else launch_right_t<float, 1, 1>(p, X, kin, kout, R, partial, st);
-        break;
-    case 2: launch_right_t<float, 2, 1>(p, X, kin, kout, R, partial, st); break;
-    case 4: launch_right_t<float, 4, 1>(p, X, kin, kout, R, partial, st); break;
-    default: launch_right_t<float, 8, 1>(p, X, kin, kout, R, partial, st); break;
+    } else {
+        launch_right_t<float, 2, 1>(p, X, kin, kout, R, partial, st);
     }
 }
 template <>
 void launch_right<double>(const Plan &p, const double *X, const Krp<double> &kin, const Krp<double> &kout, int R,
                           double *partial, hipStream_t st) {
-    if (p.NB == 1) launch_right_t<double, 1, 1>(p, X, kin, kout, R, partial, st);
-    else launch_right_t<double, 2, 1>(p, X, kin, kout, R, partial, st);
+    launch_right_t<double, 1, 1>(p, X, kin, kout, R, partial, st);
+    (void)p;
 }
 
 // Enqueue one MTTKRP (arguments already validated).

@@ -155,6 +155,78 @@ __device__ inline int64_t mod64(int64_t a, int64_t b) {
     return a % b;
 }
 
+// One-time tile build for the streaming kernels: rows [row0, row0 + nrows)
+// of K, columns [coff, coff + RP), written through store(q, c, v) (zero past
+// row_limit and past column R).  Thread t owns column t % RP and consecutive
+// runs of PR rows; for each run it decodes the first row once, steps the
+// multi-index with carries (the row order of Algorithm 1), and issues all of
+// the run's factor loads before multiplying, so a run costs about one memory
+// latency rather than one per row.  Products of more than kCursorZ factors
+// decode every row instead.
+template <typename T, int RP, int PR, typename Store>
+__device__ inline void build_tile_batched(const Krp<T> &k, int R, int coff, int64_t row0, int nrows,
+                                          int64_t row_limit, Store store) {
+    constexpr int ZM = 4;
+    const int t = threadIdx.x;
+    const int cl = t % RP;
+    const int c = coff + cl;
+    const int groups = kThreads / RP;
+    const int64_t lim = min(row_limit, k.rows);
+    const bool col_ok = c < R;
+    for (int base = (t / RP) * PR; base < nrows; base += groups * PR) {
+        T v[PR];
+        if (k.Z == 0) {
+#pragma unroll
+            for (int i = 0; i < PR; ++i) v[i] = (col_ok && row0 + base + i < lim) ? T(1) : T(0);
+        } else if (k.Z <= ZM) {
+            int64_t d[ZM];
+            const int64_t g0 = row0 + base;
+#pragma unroll
+            for (int z = 0; z < ZM; ++z) d[z] = (z < k.Z) ? mod64(div64(g0, k.stride[z]), k.J[z]) : 0;
+            T f[PR][ZM];
+#pragma unroll
+            for (int i = 0; i < PR; ++i) {
+                const bool ok = col_ok && base + i < nrows && g0 + i < lim;
+#pragma unroll
+                for (int z = 0; z < ZM; ++z) {
+                    f[i][z] = T(1);
+                    if (z < k.Z) {
+                        const rsrc_t rz = make_rsrc(k.U[z], (uint32_t)(k.J[z] * R * (int64_t)sizeof(T)));
+                        const uint32_t off = ok ? (uint32_t)((d[z] * R + c) * (int64_t)sizeof(T)) : kNoLoad;
+                        f[i][z] = buf_load1(rz, off, T(0));
+                    }
+                }
+                // next row: carry through the digits
+                bool carry = true;
+#pragma unroll
+                for (int z = 0; z < ZM; ++z) {
+                    if (carry && z < k.Z) {
+                        if (++d[z] < k.J[z]) carry = false;
+                        else d[z] = 0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < PR; ++i) {
+                T p = f[i][0];
+#pragma unroll
+                for (int z = 1; z < ZM; ++z)
+                    if (z < k.Z) p *= f[i][z];
+                v[i] = p;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PR; ++i) {
+                const int64_t g = row0 + base + i;
+                v[i] = (col_ok && base + i < nrows && g < lim) ? krp_value(k, R, g, c) : T(0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PR; ++i)
+            if (base + i < nrows) store(base + i, cl, v[i]);
+    }
+}
+
 // Two-phase tile form of the row builder for the MTTKRP kernels: rows
 // [row0, row0 + NROWS) of K, columns [coff, coff + RP).  Thread t owns
 // column t % RP and RUN = NROWS * RP / 256 consecutive rows.  fetch() issues
@@ -241,36 +313,64 @@ struct KrpTile {
     }
 };
 
+// Multi-index of one row of a Khatri-Rao product, advanced one row at a time
+// with carries (no division after the first decode).  Digit z is the row of
+// factor z (fastest first).  Only the first kCursorZ factors are tracked
+// incrementally; products of more factors fall back to decoding.
+constexpr int kCursorZ = 4;
+template <typename T>
+struct KrpCursor {
+    int64_t g;                 // row of the product
+    int64_t d[kCursorZ];       // digits of the first kCursorZ factors
+
+    __device__ inline void set(const Krp<T> &k, int64_t row) {
+        g = row;
+#pragma unroll
+        for (int z = 0; z < kCursorZ; ++z) d[z] = (z < k.Z) ? mod64(div64(row, k.stride[z]), k.J[z]) : 0;
+    }
+    __device__ inline void next(const Krp<T> &k) {
+        ++g;
+#pragma unroll
+        for (int z = 0; z < kCursorZ; ++z) {
+            if (z >= k.Z) break;
+            if (++d[z] < k.J[z]) return;
+            d[z] = 0;
+        }
+    }
+};
+
 // Raw factor values of one row of a Khatri-Rao product for NB lane columns,
 // fetched ahead of use (first ZS factors) and multiplied when needed.  The
 // row index is the same in every lane, so the index arithmetic is scalar;
 // the loads are unconditional buffer loads (a column past R reads zero).
 template <typename T, int NB>
 struct KrpRowVals {
-    static constexpr int ZS = 4;
+    static constexpr int ZS = kCursorZ;
     T f[NB][ZS];
     int64_t g;
 
-    __device__ inline void fetch(const Krp<T> &k, int R, int cbase, int64_t row) {
-        g = row;
+    __device__ inline void fetch(const Krp<T> &k, int R, int cbase, const KrpCursor<T> &cur) {
+        g = cur.g;
 #pragma unroll
         for (int z = 0; z < ZS; ++z) {
             const int zz = z < k.Z ? z : 0;  // k.Z >= 1 whenever this is used
             const rsrc_t rs = make_rsrc(k.U[zz], (uint32_t)(k.J[zz] * R * (int64_t)sizeof(T)));
-            const int64_t rowz = mod64(div64(row, k.stride[zz]), k.J[zz]);
+            const int64_t rowz = (z < k.Z) ? cur.d[z] : 0;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int c = cbase + 16 * nb;
                 const uint32_t off = (c < R) ? (uint32_t)((rowz * R + c) * (int64_t)sizeof(T)) : kNoLoad;
-                const T v = buf_load1(rs, off, T(0));
-                f[nb][z] = (z < k.Z) ? v : T(1);
+                f[nb][z] = buf_load1(rs, off, T(0));  // not touched until value(): no wait here
             }
         }
     }
     __device__ inline T value(const Krp<T> &k, int R, int cbase, int nb) const {
         const int c = cbase + 16 * nb;
         if (c >= R) return T(0);
-        T v = (f[nb][0] * f[nb][1]) * (f[nb][2] * f[nb][3]);
+        T v = f[nb][0];
+#pragma unroll
+        for (int z = 1; z < ZS; ++z)
+            if (z < k.Z) v *= f[nb][z];
         for (int z = ZS; z < k.Z; ++z) v *= k.U[z][mod64(div64(g, k.stride[z]), k.J[z]) * R + c];
         return v;
     }

@@ -58,7 +58,15 @@ namespace cpm {
 template <typename T, int NB>
 struct BlockScale {
     KrpRowVals<T, NB> next;
-    __device__ inline void prefetch(const Krp<T> &k, int R, int cbase, int64_t o) { next.fetch(k, R, cbase, o); }
+    KrpCursor<T> cur;  // outer index of the block whose values are in flight
+    __device__ inline void start(const Krp<T> &k, int R, int cbase, int64_t o) {
+        cur.set(k, o);
+        next.fetch(k, R, cbase, cur);
+    }
+    __device__ inline void advance(const Krp<T> &k, int R, int cbase) {
+        cur.next(k);
+        next.fetch(k, R, cbase, cur);
+    }
     __device__ inline T value(const Krp<T> &k, int R, int cbase, int nb) const {
         return next.value(k, R, cbase, nb);
     }
@@ -74,10 +82,14 @@ struct BlockScale {
 //   grid.y = lc + nlc * s: inner chunk lc of LC = 64*SPB entries of l_in,
 //            split s = a contiguous range of blocks_per_split outer blocks
 //   grid.z = column block (16*NB columns from c0 = z*16*NB)
-// Wave w owns entries [w*16*SPB, (w+1)*16*SPB) of the chunk for all rows.
+// A step covers 16*Q entries of every row: lane (m, kg) loads Q groups of 4
+// consecutive entries at 16q + 4kg, so one row receives Q*64 contiguous
+// bytes per step (whole cache lines for Q >= 2), and MFMA k-step (q, t)
+// pairs slot kg with entry 16q + 4kg + t.  Wave w owns entries
+// [w*16*Q*SPB, (w+1)*16*Q*SPB) of the chunk (LC = 64*Q*SPB) for all rows.
 // partial: [gridDim.y][In][R].
 // ---------------------------------------------------------------------------
-template <typename T, int NB, int MB, bool V4>
+template <typename T, int NB, int MB, bool V4, int Q = 1, int RING = 3>
 __global__ __launch_bounds__(kThreads) void k_contract_left(
     const T *__restrict__ X, int64_t IL_in, int64_t IL_out, int64_t In, int64_t n_outer, Krp<T> kin,
     Krp<T> kout, int R, int SPB, int64_t nlc, int64_t blocks_per_split, T *__restrict__ partial) {
@@ -90,7 +102,8 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, kg = lane >> 4;
     const int c0 = blockIdx.z * RP;
-    const int LC = 64 * SPB;
+    const int WS = 16 * Q;                            // entries per row per step
+    const int LC = 4 * WS * SPB;
     const int64_t lc = blockIdx.y % nlc;
     const int64_t split = blockIdx.y / nlc;
     const int64_t l0 = lc * LC;                       // first inner entry of the chunk
@@ -101,9 +114,6 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
     const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
     const bool has_out = kout.Z > 0;
 
-    // The chunk of K_in for this work-group, built once (rows past IL_in and
-    // columns past R are zero).
-    build_krp_rows<T>(kin, R, c0, RP, l0, LC, IL_in, [&](int q, int c, T v) { tile[q * PITCH + c] = v; });
 
     acc_t acc[MB][NB], tot[MB][NB];
 #pragma unroll
@@ -121,12 +131,12 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
         rok[mb] = row < In;
         rowoff[mb] = (rok[mb] ? row : 0) * IL;
     }
-    const int64_t lane_l = l0 + wave * 16 * SPB + 4 * kg;  // this lane's entries within a block: + 16*s + e
+    const int64_t lane_l = l0 + wave * WS * SPB + 4 * kg;  // this lane's entries: + WS*s + 16*q + e
 
-    auto block_base = [&](int64_t o) -> const T * {
-        const int64_t r = o / IL_out, h = o - r * IL_out;
-        return X + r * In * IL + h * IL_in;
-    };
+    // Block o = h + IL_out * r starts at X + r*In*IL + h*IL_in; the load
+    // cursor walks (h, r) with a carry instead of dividing.
+    int64_t cur_r = o_begin / IL_out, cur_h = o_begin - (o_begin / IL_out) * IL_out;
+    auto block_base = [&]() -> const T * { return X + cur_r * In * IL + cur_h * IL_in; };
 
     // load cursor
     int64_t lo = o_begin;
@@ -137,58 +147,74 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
     // kNoLoad and read zeros.  No load sits behind a branch, which lets the
     // compiler wait for exactly the step being multiplied.
     rsrc_t rs[MB];
-    auto set_block = [&](int64_t o) {
-        const T *b = block_base(o);
+    auto set_block = [&]() {
+        const T *b = block_base();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) rs[mb] = make_rsrc(b + (row_base + 16 * mb) * IL, kRsrcRange);
     };
-    if (o_begin < o_end) set_block(o_begin);
+    set_block();
     const uint32_t lane_row = (uint32_t)(m * IL);
-    auto load_step = [&](T (&a)[MB][4]) {
-        const int64_t l = lane_l + 16 * ls;
+    auto load_step = [&](T (&a)[MB][Q][4]) {
         const bool live = lo < o_end;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            if (V4) {
-                const bool ok = live && rok[mb] && l < lend;
-                const uint32_t off = ok ? (uint32_t)((lane_row + l) * sizeof(T)) : kNoLoad;
-                const acc_t v = buf_load4(rs[mb], off, T(0));
-                a[mb][0] = v[0]; a[mb][1] = v[1]; a[mb][2] = v[2]; a[mb][3] = v[3];
-            } else {
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const bool ok = live && rok[mb] && l + e < lend;
-                    const uint32_t off = ok ? (uint32_t)((lane_row + l + e) * sizeof(T)) : kNoLoad;
-                    a[mb][e] = buf_load1(rs[mb], off, T(0));
+            for (int q = 0; q < Q; ++q) {
+                const int64_t l = lane_l + WS * ls + 16 * q;
+                if (V4) {
+                    const bool ok = live && rok[mb] && l < lend;
+                    const uint32_t off = ok ? (uint32_t)((lane_row + l) * sizeof(T)) : kNoLoad;
+                    const acc_t v = buf_load4(rs[mb], off, T(0));
+                    a[mb][q][0] = v[0]; a[mb][q][1] = v[1]; a[mb][q][2] = v[2]; a[mb][q][3] = v[3];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool ok = live && rok[mb] && l + e < lend;
+                        const uint32_t off = ok ? (uint32_t)((lane_row + l + e) * sizeof(T)) : kNoLoad;
+                        a[mb][q][e] = buf_load1(rs[mb], off, T(0));
+                    }
                 }
             }
-        }
         if (++ls == SPB) {
             ls = 0;
             ++lo;
-            if (lo < o_end) set_block(lo);
+            if (++cur_h == IL_out) {
+                cur_h = 0;
+                ++cur_r;
+            }
+            set_block();
         }
     };
+
+    // Start streaming X, then build this work-group's chunk of K_in once
+    // (rows past IL_in and columns past R are zero) while those loads fly.
+    T x[RING][MB][Q][4];
+#pragma unroll
+    for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
+    build_tile_batched<T, RP, 16>(kin, R, c0, l0, LC, IL_in, [&](int q, int c, T v) { tile[q * PITCH + c] = v; });
 
     // compute cursor
     int64_t co = o_begin;
     int cs = 0;
     BlockScale<T, NB> sc;
-    if (has_out && o_begin < o_end) sc.prefetch(kout, R, c0 + m, o_begin);
+    if (has_out && o_begin < o_end) sc.start(kout, R, c0 + m, o_begin);
     __syncthreads();  // tile ready
-    auto compute_step = [&](const T (&a)[MB][4]) {
-        const T *kb = tile + (wave * 16 * SPB + 16 * cs + 4 * kg) * PITCH + m;
-        T b[4][NB];
+    auto compute_step = [&](const T (&a)[MB][Q][4]) {
+        const T *kb = tile + (wave * WS * SPB + WS * cs + 4 * kg) * PITCH + m;
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int q = 0; q < Q; ++q) {
+            T b[4][NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) b[t][nb] = kb[t * PITCH + 16 * nb];
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+                for (int nb = 0; nb < NB; ++nb) b[t][nb] = kb[(16 * q + t) * PITCH + 16 * nb];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma4(a[mb][t], b[t][nb], acc[mb][nb]);
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma4(a[mb][q][t], b[t][nb], acc[mb][nb]);
+        }
         if (++cs == SPB) {
             cs = 0;
             if (has_out) {
@@ -201,30 +227,26 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
                         acc[mb][nb] = acc_t{0, 0, 0, 0};
                     }
                 }
-                if (co + 1 < o_end) sc.prefetch(kout, R, c0 + m, co + 1);
+                if (co + 1 < o_end) sc.advance(kout, R, c0 + m);
             }
             ++co;
         }
     };
 
-    T xa[MB][4], xb[MB][4], xc[MB][4];
+    // Ring of RING register sets: RING - 1 steps in flight ahead of the one
+    // being multiplied (slot indices are compile-time after unrolling).
     const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
-    load_step(xa);
-    load_step(xb);
     int64_t st = 0;
-    for (; st + 3 <= nsteps; st += 3) {
-        load_step(xc);
-        compute_step(xa);
-        load_step(xa);
-        compute_step(xb);
-        load_step(xb);
-        compute_step(xc);
+    for (; st + RING <= nsteps; st += RING) {
+#pragma unroll
+        for (int k = 0; k < RING; ++k) {
+            load_step(x[(k + RING - 1) % RING]);
+            compute_step(x[k]);
+        }
     }
-    if (st < nsteps) {
-        compute_step(xa);
-        ++st;
-    }
-    if (st < nsteps) compute_step(xb);
+#pragma unroll
+    for (int k = 0; k < RING - 1; ++k)
+        if (st + k < nsteps) compute_step(x[k]);
     if (!has_out) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -269,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
 // 4g + e (accumulator row m' of that block is j = jt0 + 64g + 4m' + e).
 // partial: [gridDim.y][J][R].
 // ---------------------------------------------------------------------------
-template <typename T, int NB, int MJ, bool V4>
+template <typename T, int NB, int MJ, bool V4, int RING = 3>
 __global__ __launch_bounds__(kThreads) void k_contract_right(
     const T *__restrict__ X, int64_t J, int64_t IR_in, int64_t n_outer, Krp<T> kin, Krp<T> kout, int R,
     int SPB, int64_t nlc, int64_t blocks_per_split, T *__restrict__ partial) {
@@ -292,7 +314,6 @@ __global__ __launch_bounds__(kThreads) void k_contract_right(
     const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
     const bool has_out = kout.Z > 0;
 
-    build_krp_rows<T>(kin, R, c0, RP, r0, LC, IR_in, [&](int q, int c, T v) { tile[q * PITCH + c] = v; });
 
     acc_t acc[MJ][4][NB], tot[MJ][4][NB];
 #pragma unroll
@@ -352,10 +373,15 @@ __global__ __launch_bounds__(kThreads) void k_contract_right(
         }
     };
 
+    T x[RING][4][MJ][4];
+#pragma unroll
+    for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
+    build_tile_batched<T, RP, 16>(kin, R, c0, r0, LC, IR_in, [&](int q, int c, T v) { tile[q * PITCH + c] = v; });
+
     int64_t co = o_begin;
     int cs = 0;
     BlockScale<T, NB> sc;
-    if (has_out && o_begin < o_end) sc.prefetch(kout, R, c0 + m, o_begin);
+    if (has_out && o_begin < o_end) sc.start(kout, R, c0 + m, o_begin);
     __syncthreads();
     auto compute_step = [&](const T (&a)[4][MJ][4]) {
         const T *kb = tile + (wave * 16 * SPB + 16 * cs + 4 * kg) * PITCH + m;
@@ -386,30 +412,24 @@ __global__ __launch_bounds__(kThreads) void k_contract_right(
                             acc[g][e][nb] = acc_t{0, 0, 0, 0};
                         }
                 }
-                if (co + 1 < o_end) sc.prefetch(kout, R, c0 + m, co + 1);
+                if (co + 1 < o_end) sc.advance(kout, R, c0 + m);
             }
             ++co;
         }
     };
 
-    T xa[4][MJ][4], xb[4][MJ][4], xc[4][MJ][4];
     const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
-    load_step(xa);
-    load_step(xb);
     int64_t st = 0;
-    for (; st + 3 <= nsteps; st += 3) {
-        load_step(xc);
-        compute_step(xa);
-        load_step(xa);
-        compute_step(xb);
-        load_step(xb);
-        compute_step(xc);
+    for (; st + RING <= nsteps; st += RING) {
+#pragma unroll
+        for (int k = 0; k < RING; ++k) {
+            load_step(x[(k + RING - 1) % RING]);
+            compute_step(x[k]);
+        }
     }
-    if (st < nsteps) {
-        compute_step(xa);
-        ++st;
-    }
-    if (st < nsteps) compute_step(xb);
+#pragma unroll
+    for (int k = 0; k < RING - 1; ++k)
+        if (st + k < nsteps) compute_step(x[k]);
     if (!has_out) {
 #pragma unroll
         for (int g = 0; g < MJ; ++g)
