@@ -1,0 +1,427 @@
+// Split-bfloat16 MTTKRP: the tensor is stored as two bfloat16 planes, hi and
+// lo, with value hi + lo (about 16 significant bits of the float32 it came
+// from).  The Khatri-Rao product values are formed in float32 and split the
+// same way inside the kernel.  Each contraction step multiplies
+//     Xh*Kh + Xh*Kl + Xl*Kh
+// on the 16x16x32 bf16 MFMA with float32 accumulation; the dropped Xl*Kl
+// term is below 2^-16 of each product.  This recovers float32-level accuracy
+// at a fraction of the float32 MFMA cost, and the tensor still moves only
+// 4 bytes per entry.
+//
+// The work decomposition is that of the float32 kernels in
+// mttkrp_kernels.hpp (resident inner Khatri-Rao tile, X streamed block by
+// block over the outer index, per-block scaling for the outer factors).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace cpm {
+
+__device__ inline bf16x8 as_bf16x8(f32x4 raw) { return __builtin_bit_cast(bf16x8, raw); }
+
+// One 16-byte buffer load of 8 consecutive bf16 values.
+__device__ inline f32x4 buf_load_raw16(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// 8 consecutive bf16 values read one at a time (unaligned rows); lanes past
+// the row end read zeros.
+__device__ inline f32x4 buf_load_raw16_scalar(rsrc_t r, uint32_t off, int64_t l, int64_t lend) {
+    u16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const uint32_t oe = (off != kNoLoad && l + e < lend) ? off + 2 * e : kNoLoad;
+        v[e] = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, oe, 0, 0);
+    }
+    return __builtin_bit_cast(f32x4, v);
+}
+
+// ---------------------------------------------------------------------------
+// Left-first split-bf16 contraction (internal and last modes).  Geometry as
+// k_contract_left: X viewed as X[r][i][h][l_in], outer block o = h + IL_out*r.
+//   grid.x = row tile (16*MB rows), grid.y = lc + nlc*split, grid.z = column
+//   block (16*NB columns).
+// A step covers 32*Q entries of every row: lane (m, kg) loads Q groups of 8
+// consecutive entries at 32q + 8kg from each plane (one 16x16x32 MFMA k-step
+// per group), so a row receives Q*64 contiguous bytes per plane.  Wave w owns
+// entries [w*32*Q*SPB, (w+1)*32*Q*SPB) of the chunk (LC = 128*Q*SPB).
+// The tile holds K_in split into bf16 planes, stored column-major
+// (Kt[c][l]) so the B operand of a k-step is one 16-byte LDS read.
+// partial: [gridDim.y][In][R] float32.
+// ---------------------------------------------------------------------------
+template <int NB, int MB, int Q, bool V8, int RING = 3>
+__global__ __launch_bounds__(kThreads) void k_contract_left_bf16(
+    const uint16_t *__restrict__ Xp, int64_t I, int64_t IL_in, int64_t IL_out, int64_t In, int64_t n_outer,
+    Krp<float> kin, Krp<float> kout, int R, int SPB, int64_t nlc, int64_t blocks_per_split,
+    float *__restrict__ partial) {
+    constexpr int RP = NB * 16;
+    const int WS = 32 * Q;
+    const int LC = 4 * WS * SPB;
+    const int LCP = LC + 8;  // bf16 row pitch of the transposed tile (16-byte pad)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint16_t *kth = reinterpret_cast<uint16_t *>(smem_raw);
+    uint16_t *ktl = kth + RP * LCP;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    const int c0 = blockIdx.z * RP;
+    const int64_t lc = blockIdx.y % nlc;
+    const int64_t split = blockIdx.y / nlc;
+    const int64_t l0 = lc * LC;
+    const int64_t lend = min(IL_in, l0 + LC);
+    const int64_t IL = IL_in * IL_out;
+    const int64_t row_base = (int64_t)blockIdx.x * 16 * MB;
+    const int64_t o_begin = split * blocks_per_split;
+    const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
+    const bool has_out = kout.Z > 0;
+
+    f32x4 acc[MB][NB], tot[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            acc[mb][nb] = f32x4{0, 0, 0, 0};
+            tot[mb][nb] = f32x4{0, 0, 0, 0};
+        }
+    bool rok[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) rok[mb] = row_base + 16 * mb + m < In;
+    const uint32_t lane_row = (uint32_t)(m * IL);
+    const int64_t lane_l = l0 + wave * WS * SPB + 8 * kg;
+
+    int64_t cur_r = o_begin / IL_out, cur_h = o_begin - (o_begin / IL_out) * IL_out;
+    rsrc_t rh[MB], rl[MB];
+    auto set_block = [&]() {
+        const int64_t b = cur_r * In * IL + cur_h * IL_in;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int64_t e = b + (row_base + 16 * mb) * IL;
+            rh[mb] = make_rsrc(Xp + e, kRsrcRange);
+            rl[mb] = make_rsrc(Xp + I + e, kRsrcRange);
+        }
+    };
+    set_block();
+
+    int64_t lo = o_begin;
+    int ls = 0;
+    // a[mb][q][0] = hi, a[mb][q][1] = lo
+    auto load_step = [&](f32x4 (&a)[MB][Q][2]) {
+        const bool live = lo < o_end;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int64_t l = lane_l + WS * ls + 32 * q;
+                const bool ok = live && rok[mb] && l < lend;
+                const uint32_t off = ok ? (uint32_t)((lane_row + l) * 2) : kNoLoad;
+                if (V8) {
+                    a[mb][q][0] = buf_load_raw16(rh[mb], off);
+                    a[mb][q][1] = buf_load_raw16(rl[mb], off);
+                } else {
+                    a[mb][q][0] = buf_load_raw16_scalar(rh[mb], off, l, lend);
+                    a[mb][q][1] = buf_load_raw16_scalar(rl[mb], off, l, lend);
+                }
+            }
+        if (++ls == SPB) {
+            ls = 0;
+            ++lo;
+            if (++cur_h == IL_out) {
+                cur_h = 0;
+                ++cur_r;
+            }
+            set_block();
+        }
+    };
+
+    f32x4 x[RING][MB][Q][2];
+#pragma unroll
+    for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
+    // Build this work-group's chunk of K_in once: float32 values split into
+    // the hi/lo planes of the transposed tile.
+    build_tile_batched<float, RP, 16>(kin, R, c0, l0, LC, IL_in, [&](int q, int c, float v) {
+        const uint16_t h = bf16_rne_bits(v);
+        kth[c * LCP + q] = h;
+        ktl[c * LCP + q] = bf16_rne_bits(v - bf16_bits_to_float(h));
+    });
+
+    int64_t co = o_begin;
+    int cs = 0;
+    KrpRowVals<float, NB> sv;
+    KrpCursor<float> scur;
+    if (has_out && o_begin < o_end) {
+        scur.set(kout, o_begin);
+        sv.fetch(kout, R, c0 + m, scur);
+    }
+    __syncthreads();
+
+    auto compute_step = [&](const f32x4 (&a)[MB][Q][2]) {
+        const int kbase = wave * WS * SPB + WS * cs + 8 * kg;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int c = 16 * nb + m;
+                const bf16x8 bh = as_bf16x8(*reinterpret_cast<const f32x4 *>(kth + c * LCP + kbase + 32 * q));
+                const bf16x8 bl = as_bf16x8(*reinterpret_cast<const f32x4 *>(ktl + c * LCP + kbase + 32 * q));
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    const bf16x8 ah = as_bf16x8(a[mb][q][0]);
+                    const bf16x8 al = as_bf16x8(a[mb][q][1]);
+                    acc[mb][nb] = mfma_bf16(ah, bh, acc[mb][nb]);
+                    acc[mb][nb] = mfma_bf16(ah, bl, acc[mb][nb]);
+                    acc[mb][nb] = mfma_bf16(al, bh, acc[mb][nb]);
+                }
+            }
+        }
+        if (++cs == SPB) {
+            cs = 0;
+            if (has_out) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const float s = sv.value(kout, R, c0 + m, nb);
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb) {
+                        tot[mb][nb] += acc[mb][nb] * s;
+                        acc[mb][nb] = f32x4{0, 0, 0, 0};
+                    }
+                }
+                if (co + 1 < o_end) {
+                    scur.next(kout);
+                    sv.fetch(kout, R, c0 + m, scur);
+                }
+            }
+            ++co;
+        }
+    };
+
+    const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
+    int64_t st = 0;
+    for (; st + RING <= nsteps; st += RING) {
+#pragma unroll
+        for (int k = 0; k < RING; ++k) {
+            load_step(x[(k + RING - 1) % RING]);
+            compute_step(x[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RING - 1; ++k)
+        if (st + k < nsteps) compute_step(x[k]);
+    if (!has_out) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) tot[mb][nb] = acc[mb][nb];
+    }
+
+    __syncthreads();
+    float *red = reinterpret_cast<float *>(smem_raw);  // [wave][mb][nb][j][lane]
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                red[(((wave * MB + mb) * NB + nb) * 4 + j) * 64 + lane] = tot[mb][nb][j];
+    __syncthreads();
+    constexpr int PER_WAVE = MB * NB * 4 * 64;
+    for (int e = tid; e < PER_WAVE; e += kThreads) {
+        const int ln = e & 63, j = (e >> 6) & 3, blk = e >> 8;
+        const int nb = blk % NB, mb = blk / NB;
+        const float sum = ((red[e] + red[PER_WAVE + e]) + red[2 * PER_WAVE + e]) + red[3 * PER_WAVE + e];
+        const int64_t row = row_base + 16 * mb + acc_row<float>(ln, j);
+        const int c = c0 + 16 * nb + (ln & 15);
+        if (row < In && c < R) partial[((int64_t)blockIdx.y * In + row) * R + c] = sum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Right-first split-bf16 contraction (mode 0, and internal modes with a short
+// left product).  Geometry as k_contract_right: X viewed as X[o][r_in][j],
+// T(j, c) = sum_o S(o, c) sum_{r_in} X[o][r_in][j] K_in(r_in, c).
+// The contracted index r_in is the strided one, while the bf16 MFMA packs 8
+// consecutive k values per lane, so every step's X tile (32 rows x 64 j, both
+// planes) is loaded with 16-byte loads along j and written to LDS transposed
+// (Xt[j][r]); lanes then read 8 consecutive r of one j in one 16-byte read.
+// The waves split the rank columns (WN ways) and the 4 j-blocks (WM ways),
+// so each wave owns distinct output blocks.  X steps are kept DX deep in
+// flight in registers; the LDS X tile is double-buffered.
+//   grid.x = j tile of 64, grid.y = lc + nlc*split (inner chunk of
+//   LC = 32*SPB rows, split of the outer blocks), grid.z = column block.
+// partial: [gridDim.y][J][R] float32.
+// ---------------------------------------------------------------------------
+template <int NB, bool V8, int DX = 6>
+__global__ __launch_bounds__(kThreads) void k_contract_right_bf16(
+    const uint16_t *__restrict__ Xp, int64_t I, int64_t J, int64_t IR_in, int64_t n_outer, Krp<float> kin,
+    Krp<float> kout, int R, int SPB, int64_t nlc, int64_t blocks_per_split, float *__restrict__ partial) {
+    constexpr int RP = NB * 16;
+    constexpr int WN = NB < 4 ? NB : 4;  // waves along rank blocks
+    constexpr int WM = 4 / WN;           // waves along j blocks
+    constexpr int NBW = NB / WN;         // rank blocks per wave
+    constexpr int MBW = 4 / WM;          // j blocks per wave
+    constexpr int JT = 64, RS = 32, XP = RS + 8;
+    const int LC = RS * SPB;
+    const int LCP = LC + 8;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint16_t *kth = reinterpret_cast<uint16_t *>(smem_raw);
+    uint16_t *ktl = kth + RP * LCP;
+    uint16_t *xt = ktl + RP * LCP;  // [2 buffers][2 planes][JT][XP]
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, so the X descriptor stays scalar
+    const int m = lane & 15, kg = lane >> 4;
+    const int wn = wave % WN, wm = wave / WN;
+    const int c0 = blockIdx.z * RP;
+    const int64_t jt0 = (int64_t)blockIdx.x * JT;
+    const int64_t lc = blockIdx.y % nlc;
+    const int64_t split = blockIdx.y / nlc;
+    const int64_t r0 = lc * LC;
+    const int64_t rend = min(IR_in, r0 + LC);
+    const int64_t o_begin = split * blocks_per_split;
+    const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
+    const bool has_out = kout.Z > 0;
+
+    // X tile loader: thread -> (plane, 8-wide j group, row pair)
+    const int plane = wave >> 1, tt = tid & 127, jg = tt & 7, rp = tt >> 3;  // rp in [0, 16)
+    const bool jok = V8 ? (jt0 + 8 * jg < J) : true;
+    int64_t lo = o_begin;
+    int ls = 0;
+    rsrc_t rx = make_rsrc(Xp + (int64_t)plane * I + (o_begin < o_end ? o_begin : 0) * IR_in * J + r0 * J + jt0,
+                          kRsrcRange);
+    auto load_step = [&](f32x4 (&a)[2]) {
+        const bool live = lo < o_end;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t rl = (int64_t)RS * ls + 2 * rp + h;  // row within the chunk
+            const bool ok = live && r0 + rl < rend;
+            if (V8) {
+                const uint32_t off = (ok && jok) ? (uint32_t)((rl * J + 8 * jg) * 2) : kNoLoad;
+                a[h] = buf_load_raw16(rx, off);
+            } else {
+                const uint32_t off = ok ? (uint32_t)((rl * J + 8 * jg) * 2) : kNoLoad;
+                a[h] = buf_load_raw16_scalar(rx, off, jt0 + 8 * jg, J);
+            }
+        }
+        if (++ls == SPB) {
+            ls = 0;
+            ++lo;
+            if (lo < o_end)
+                rx = make_rsrc(Xp + (int64_t)plane * I + lo * IR_in * J + r0 * J + jt0, kRsrcRange);
+        }
+    };
+    // Transposed write: the two rows of this thread are adjacent in r, so each
+    // j gets one 32-bit (2 x bf16) store.
+    auto write_tile = [&](const f32x4 (&a)[2], int buf) {
+        const u16x8 v0 = __builtin_bit_cast(u16x8, a[0]);
+        const u16x8 v1 = __builtin_bit_cast(u16x8, a[1]);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(xt + ((buf * 2 + plane) * JT + 8 * jg) * XP + 2 * rp);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dst[e * XP / 2] = (uint32_t)v0[e] | ((uint32_t)v1[e] << 16);
+    };
+
+    f32x4 acc[MBW][NBW], tot[MBW][NBW];
+#pragma unroll
+    for (int a = 0; a < MBW; ++a)
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+            acc[a][b] = f32x4{0, 0, 0, 0};
+            tot[a][b] = f32x4{0, 0, 0, 0};
+        }
+
+    f32x4 x[DX][2];
+#pragma unroll
+    for (int k = 0; k < DX; ++k) load_step(x[k]);
+    build_tile_batched<float, RP, 16>(kin, R, c0, r0, LC, IR_in, [&](int q, int c, float v) {
+        const uint16_t hb = bf16_rne_bits(v);
+        kth[c * LCP + q] = hb;
+        ktl[c * LCP + q] = bf16_rne_bits(v - bf16_bits_to_float(hb));
+    });
+    const int cbase = c0 + 16 * wn * NBW + m;
+    int64_t co = o_begin;
+    int cs = 0;
+    KrpRowVals<float, NBW> sv;
+    KrpCursor<float> scur;
+    if (has_out && o_begin < o_end) {
+        scur.set(kout, o_begin);
+        sv.fetch(kout, R, cbase, scur);
+    }
+
+    auto compute_step = [&](int buf) {
+        const uint16_t *xb = xt + buf * 2 * JT * XP;
+#pragma unroll
+        for (int a = 0; a < MBW; ++a) {
+            const int j = 16 * (wm * MBW + a) + m;
+            const bf16x8 ah = as_bf16x8(*reinterpret_cast<const f32x4 *>(xb + j * XP + 8 * kg));
+            const bf16x8 al = as_bf16x8(*reinterpret_cast<const f32x4 *>(xb + JT * XP + j * XP + 8 * kg));
+#pragma unroll
+            for (int b = 0; b < NBW; ++b) {
+                const int c = 16 * (wn * NBW + b) + m;
+                const int koff = c * LCP + RS * cs + 8 * kg;
+                const bf16x8 bh = as_bf16x8(*reinterpret_cast<const f32x4 *>(kth + koff));
+                const bf16x8 bl = as_bf16x8(*reinterpret_cast<const f32x4 *>(ktl + koff));
+                acc[a][b] = mfma_bf16(ah, bh, acc[a][b]);
+                acc[a][b] = mfma_bf16(ah, bl, acc[a][b]);
+                acc[a][b] = mfma_bf16(al, bh, acc[a][b]);
+            }
+        }
+        if (++cs == SPB) {
+            cs = 0;
+            if (has_out) {
+#pragma unroll
+                for (int b = 0; b < NBW; ++b) {
+                    const float sval = sv.value(kout, R, cbase, b);
+#pragma unroll
+                    for (int a = 0; a < MBW; ++a) {
+                        tot[a][b] += acc[a][b] * sval;
+                        acc[a][b] = f32x4{0, 0, 0, 0};
+                    }
+                }
+                if (co + 1 < o_end) {
+                    scur.next(kout);
+                    sv.fetch(kout, R, cbase, scur);
+                }
+            }
+            ++co;
+        }
+    };
+
+    const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
+    if (nsteps > 0) write_tile(x[0], 0);
+    __syncthreads();
+    // step st is computed from LDS buffer st & 1; its registers were x[st % DX]
+    int64_t st = 0;
+    for (; st + DX <= nsteps; st += DX) {
+#pragma unroll
+        for (int k = 0; k < DX; ++k) {
+            compute_step((int)((st + k) & 1));
+            if (st + k + 1 < nsteps) write_tile(x[(k + 1) % DX], (int)((st + k + 1) & 1));
+            load_step(x[k]);  // step st + k + DX
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DX; ++k) {
+        if (st + k < nsteps) {
+            compute_step((int)((st + k) & 1));
+            if (st + k + 1 < nsteps) write_tile(x[(k + 1) % DX], (int)((st + k + 1) & 1));
+            __syncthreads();
+        }
+    }
+    if (!has_out) {
+#pragma unroll
+        for (int a = 0; a < MBW; ++a)
+#pragma unroll
+            for (int b = 0; b < NBW; ++b) tot[a][b] = acc[a][b];
+    }
+#pragma unroll
+    for (int a = 0; a < MBW; ++a)
+#pragma unroll
+        for (int b = 0; b < NBW; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t j = jt0 + 16 * (wm * MBW + a) + acc_row<float>(lane, q);
+                const int c = c0 + 16 * (wn * NBW + b) + m;
+                if (j < J && c < R) partial[((int64_t)blockIdx.y * J + j) * R + c] = tot[a][b][q];
+            }
+}
+
+}  // namespace cpm

@@ -10,6 +10,7 @@
 
 #include "../../include/cpmttkrp.h"
 #include "als_kernels.hpp"
+#include "bf16_kernels.hpp"
 #include "mttkrp_kernels.hpp"
 
 using namespace cpm;
@@ -102,6 +103,70 @@ int pow2_at_least(int v) {
     return p;
 }
 
+// Split-bf16 tiling.  Left-first once the left product is at least one
+// 32-entry k-step long; otherwise right-first (X tiles transposed in LDS).
+constexpr size_t kBf16XtBytes = 2 * 2 * 64 * 40 * 2;  // double-buffered hi/lo X tile of the right kernel
+
+void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void *X) {
+    const int RPtot = (R + 15) / 16 * 16;
+    const int nb = RPtot / 16;
+    p.NB = nb <= 8 ? pow2_at_least(nb) : 8;
+    p.ncb = nb <= 8 ? 1 : (int)ceil_div(nb, 8);
+    const int RP = p.NB * 16;
+    const int64_t I = p.IL * p.In * p.IR;
+    if (p.IL >= 32) {
+        p.kind = kBf16Left;
+        p.MB = p.NB >= 4 ? 1 : 2;
+        while (p.MB > 1 && 16 * p.MB / 2 >= p.In) p.MB /= 2;
+        const int64_t lcmax =
+            std::max<int64_t>(128, std::min<int64_t>(512, (int64_t)(kTileBytes / (4 * RP) - 8) / 128 * 128));
+        int q = 0;
+        p.G_in = 1;
+        while (q < mode && p.G_in * dims[q] <= lcmax) p.G_in *= dims[q++];
+        if (q == 0) p.G_in = dims[q++];  // one long mode, cut into chunks
+        p.p = q;
+        p.G_out = p.IL / p.G_in;
+        p.n_outer = p.G_out * p.IR;
+        p.Q = (p.NB >= 8 || p.G_in <= 128) ? 1 : 2;
+        const int64_t unit = 128 * p.Q;
+        p.LC = (int)std::min<int64_t>(std::max<int64_t>(unit, lcmax / unit * unit), ceil_div(p.G_in, unit) * unit);
+        p.SPB = p.LC / (int)unit;
+        p.nlc = ceil_div(p.G_in, p.LC);
+        p.ntiles = ceil_div(p.In, 16 * p.MB);
+        const size_t tile = (size_t)4 * RP * (p.LC + 8);
+        const size_t red = (size_t)4 * p.MB * p.NB * 256 * 4;
+        p.lds = std::max(tile, red);
+        p.v4 = (p.G_in % 8 == 0) && (I % 8 == 0) && ((uintptr_t)X % 16 == 0);
+        p.max_offset = (15 * p.IL + p.G_in + 8) * 2;
+        p.J = p.In;
+    } else {
+        p.kind = kBf16Right;
+        p.J = p.In * p.IL;
+        const int64_t lcmax = std::max<int64_t>(
+            32, std::min<int64_t>(512, ((int64_t)((kTileBytes - kBf16XtBytes) / (4 * RP)) - 8) / 32 * 32));
+        int q = mode + 1;
+        p.G_in = 1;
+        while (q < N && p.G_in * dims[q] <= lcmax) p.G_in *= dims[q++];
+        if (q == mode + 1 && q < N) p.G_in = dims[q++];
+        p.p = q;
+        p.n_outer = p.IR / p.G_in;
+        p.LC = (int)std::min<int64_t>(lcmax, ceil_div(p.G_in, 32) * 32);
+        p.SPB = p.LC / 32;
+        p.nlc = ceil_div(p.G_in, p.LC);
+        p.ntiles = ceil_div(p.J, 64);
+        p.lds = (size_t)4 * RP * (p.LC + 8) + kBf16XtBytes;
+        p.v4 = (p.J % 8 == 0) && (I % 8 == 0) && ((uintptr_t)X % 16 == 0);
+        p.max_offset = ((int64_t)p.LC * p.J + 64 + 8) * 2;
+    }
+    int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.nlc * p.ncb));
+    S = std::min(S, p.n_outer);
+    p.bps = ceil_div(p.n_outer, S);
+    p.S = ceil_div(p.n_outer, p.bps);
+    p.reduce = p.S * p.nlc > 1 || (p.kind == kBf16Right && mode > 0);
+    const int64_t rows = p.kind == kBf16Left ? p.In : p.J;
+    p.partial_bytes = p.reduce ? (size_t)p.S * p.nlc * rows * R * 4 : 0;
+}
+
 Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const void *X) {
     Plan p{};
     p.IL = 1;
@@ -113,7 +178,7 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
     const int RPtot = (R + 15) / 16 * 16;
     const bool bf = dt == CPM_BF16X2;
     if (bf) {
-        p.kind = kBf16Left;
+        plan_bf16(p, dims, N, R, mode, X);
         return p;
     }
     const bool left = p.IL >= 16;
@@ -328,12 +393,96 @@ cpm_status run_mttkrp_t(const Plan &p, const void *Xv, const int64_t *dims, int 
     return CPM_OK;
 }
 
+template <int NB, int MB, int Q>
+void launch_left_bf16_t(const Plan &p, const uint16_t *X, int64_t I, const Krp<float> &kin, const Krp<float> &kout,
+                        int R, float *partial, hipStream_t st) {
+    dim3 grid((unsigned)p.ntiles, (unsigned)(p.S * p.nlc), (unsigned)p.ncb);
+    if (p.v4)
+        hipLaunchKernelGGL((k_contract_left_bf16<NB, MB, Q, true>), grid, dim3(kThreads), p.lds, st, X, I, p.G_in,
+                           p.G_out, p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+    else
+        hipLaunchKernelGGL((k_contract_left_bf16<NB, MB, Q, false>), grid, dim3(kThreads), p.lds, st, X, I, p.G_in,
+                           p.G_out, p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+}
+
+template <int NB, int MB>
+void launch_left_bf16_q(const Plan &p, const uint16_t *X, int64_t I, const Krp<float> &kin, const Krp<float> &kout,
+                        int R, float *partial, hipStream_t st) {
+    if (p.Q == 2) launch_left_bf16_t<NB, MB, 2>(p, X, I, kin, kout, R, partial, st);
+    else launch_left_bf16_t<NB, MB, 1>(p, X, I, kin, kout, R, partial, st);
+}
+
+template <int NB>
+void launch_left_bf16_m(const Plan &p, const uint16_t *X, int64_t I, const Krp<float> &kin, const Krp<float> &kout,
+                        int R, float *partial, hipStream_t st) {
+    if (p.MB == 2) launch_left_bf16_q<NB, 2>(p, X, I, kin, kout, R, partial, st);
+    else launch_left_bf16_q<NB, 1>(p, X, I, kin, kout, R, partial, st);
+}
+
+template <int NB>
+void launch_right_bf16_t(const Plan &p, const uint16_t *X, int64_t I, const Krp<float> &kin,
+                         const Krp<float> &kout, int R, float *partial, hipStream_t st) {
+    dim3 grid((unsigned)p.ntiles, (unsigned)(p.S * p.nlc), (unsigned)p.ncb);
+    if (p.v4)
+        hipLaunchKernelGGL((k_contract_right_bf16<NB, true>), grid, dim3(kThreads), p.lds, st, X, I, p.J, p.G_in,
+                           p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+    else
+        hipLaunchKernelGGL((k_contract_right_bf16<NB, false>), grid, dim3(kThreads), p.lds, st, X, I, p.J, p.G_in,
+                           p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+}
+
+cpm_status run_mttkrp_bf16(const Plan &p, const void *Xv, const int64_t *dims, int N, const void *const *factors,
+                           int R, int mode, void *outv, void *ws, hipStream_t st) {
+    int in_modes[CPM_MAX_MODES], out_modes[CPM_MAX_MODES], left_modes[CPM_MAX_MODES];
+    int nin = 0, nout = 0, nleft = 0;
+    for (int k = 0; k < mode; ++k) left_modes[nleft++] = k;
+    if (p.kind == kBf16Left) {
+        for (int k = 0; k < p.p; ++k) in_modes[nin++] = k;
+        for (int k = p.p; k < mode; ++k) out_modes[nout++] = k;
+        for (int k = mode + 1; k < N; ++k) out_modes[nout++] = k;
+    } else {
+        for (int k = mode + 1; k < p.p; ++k) in_modes[nin++] = k;
+        for (int k = p.p; k < N; ++k) out_modes[nout++] = k;
+    }
+    const Krp<float> kin = krp_of<float>(factors, dims, in_modes, nin);
+    const Krp<float> kout = krp_of<float>(factors, dims, out_modes, nout);
+    const uint16_t *X = reinterpret_cast<const uint16_t *>(Xv);
+    const int64_t I = p.IL * p.In * p.IR;
+    float *out = reinterpret_cast<float *>(outv);
+    float *partial = p.reduce ? reinterpret_cast<float *>(ws) : out;
+    if (p.kind == kBf16Left) {
+        switch (p.NB) {
+        case 1: launch_left_bf16_m<1>(p, X, I, kin, kout, R, partial, st); break;
+        case 2: launch_left_bf16_m<2>(p, X, I, kin, kout, R, partial, st); break;
+        case 4: launch_left_bf16_q<4, 1>(p, X, I, kin, kout, R, partial, st); break;
+        default: launch_left_bf16_t<8, 1, 1>(p, X, I, kin, kout, R, partial, st); break;
+        }
+        LAUNCH_CHECK("k_contract_left_bf16");
+    } else {
+        switch (p.NB) {
+        case 1: launch_right_bf16_t<1>(p, X, I, kin, kout, R, partial, st); break;
+        case 2: launch_right_bf16_t<2>(p, X, I, kin, kout, R, partial, st); break;
+        case 4: launch_right_bf16_t<4>(p, X, I, kin, kout, R, partial, st); break;
+        default: launch_right_bf16_t<8>(p, X, I, kin, kout, R, partial, st); break;
+        }
+        LAUNCH_CHECK("k_contract_right_bf16");
+    }
+    if (p.reduce) {
+        const int64_t rows_per_slice = (p.kind == kBf16Left) ? p.In : p.J;
+        const Krp<float> kred = krp_of<float>(factors, dims, left_modes, p.kind == kBf16Left ? 0 : nleft);
+        const int64_t il = (p.kind == kBf16Left) ? 1 : p.IL;
+        hipLaunchKernelGGL((k_reduce<float, float>), dim3((unsigned)ceil_div(p.In * R, 64)), dim3(kThreads), 0, st,
+                           partial, p.S * p.nlc, rows_per_slice, p.In, il, kred, R, out);
+        LAUNCH_CHECK("k_reduce");
+    }
+    return CPM_OK;
+}
+
 cpm_status run_mttkrp(const Plan &p, const void *X, const int64_t *dims, int N, const void *const *factors,
                       int R, int mode, void *out, cpm_dtype dt, void *ws, hipStream_t st) {
     if (dt == CPM_F32) return run_mttkrp_t<float>(p, X, dims, N, factors, R, mode, out, ws, st);
     if (dt == CPM_F64) return run_mttkrp_t<double>(p, X, dims, N, factors, R, mode, out, ws, st);
-    (void)p; (void)X; (void)dims; (void)N; (void)factors; (void)R; (void)mode; (void)out; (void)ws; (void)st;
-    return fail(CPM_EUNSUPPORTED, "bf16 pair MTTKRP not built yet");
+    return run_mttkrp_bf16(p, X, dims, N, factors, R, mode, out, ws, st);
 }
 
 cpm_status validate_mttkrp(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
