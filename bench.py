@@ -10,7 +10,7 @@ and the FP64 oracle timed on the host cores as a CPU baseline.
 Extra measurements (on by default, --quick skips them): the CP-ALS sweep on
 the same tensor, the 256x256x512x32 correlation-style tensor at R = 64 in
 float32 and at R = 128 in split bf16 against float32, and CP-gradient
-evaluations per second on the 64^5 tensor.
+evaluations per second on the 64^5 tensor in float32 and split bf16.
 """
 import argparse
 import hashlib
@@ -116,24 +116,30 @@ def shape_class(dims, n):
     return "internal (fused 2-step)"
 
 
-def cpu_baseline(X, dims, U):
-    """The FP64 oracle on the host cores, all modes of the main tensor once."""
+def cpu_baseline(X, dims, U, min_seconds=10.0, max_reps=40):
+    """The FP64 oracle on the host cores: all modes of the main tensor,
+    repeated until at least `min_seconds` of CPU work (bounded)."""
     import numpy as np
 
     from oracle import oracle as O
     Xh = X.cpu().numpy().ravel()
     Uh = [u.cpu().numpy().astype(np.float64) for u in U]
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    reps = 0
     t0 = time.perf_counter()
-    for n in range(len(dims)):
-        O.mttkrp(Xh, dims, Uh, n, nthreads=threads)
+    while reps < max_reps:
+        for n in range(len(dims)):
+            O.mttkrp(Xh, dims, Uh, n, nthreads=threads)
+        reps += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
     dt = time.perf_counter() - t0
     I = Xh.size
     R = Uh[0].shape[1]
-    flops = len(dims) * 2.0 * I * R
+    flops = reps * len(dims) * 2.0 * I * R
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": "all %d modes of the full %s tensor, R=%d, once (%.1f s)" % (
-                len(dims), "x".join(map(str, dims)), R, dt)}
+            "sample": "all %d modes of the full %s float32 tensor, R=%d, repeated %d times (%.1f s)" % (
+                len(dims), "x".join(map(str, dims)), R, reps, dt)}
 
 
 def main():
@@ -218,46 +224,73 @@ def extra_measurements(torch, _abi, inputs, X2, dims2, U2, stream):
     torch.cuda.synchronize()
     out["cp_als_sweep_512cube_r32"] = {"ms": round(t0.elapsed_time(t1) / reps, 3), "fit": round(fit, 6)}
 
-    # 256x256x512x32 correlation-style tensor: float32 at R=64, split bf16 vs float32 at R=128.
+    # 256x256x512x32 correlation-style tensor: float32 at R=64; split bf16
+    # against float32 at R=128 (same tensor, same factors).
     dims3 = (256, 256, 512, 32)
+    I3 = 256 * 256 * 512 * 32
     X3 = inputs.symmetric_pair_tensor(dims3, seed=6, device="cuda")
-    for R, tag in [(64, "fp32_r64")]:
-        U3 = inputs.normal_factors(dims3, R, seed=7, device="cuda")
+    P3 = _abi.split_bf16(X3.reshape(-1))
+    runs = {}
+    for R, dt, tag in [(64, _abi.CPM_F32, "fp32_r64"), (128, _abi.CPM_F32, "fp32_r128"),
+                       (128, _abi.CPM_BF16X2, "bf16x2_r128")]:
+        U3 = inputs.normal_factors(dims3, R, seed=7 if R == 64 else 8, device="cuda")
         outs = [torch.empty((d, R), device=dev) for d in dims3]
-        ws3 = torch.empty(max(_abi.mttkrp_workspace_bytes(dims3, R, n, _abi.CPM_F32) for n in range(4)) + 256,
+        ws3 = torch.empty(max(_abi.mttkrp_workspace_bytes(dims3, R, n, dt) for n in range(4)) + 256,
                           dtype=torch.uint8, device=dev)
-        step_ms, per_mode = time_modes(torch, _abi, X3, dims3, U3, outs, ws3, _abi.CPM_F32, 5, 1, stream)
-        I = 256 * 256 * 512 * 32
-        fl = 2.0 * I * R
-        out["sym4d_" + tag] = {
-            "ms_all_modes": round(step_ms, 3),
-            "per_mode_us": [round(t * 1e3, 1) for t in per_mode],
-            "per_mode_TFLOP/s": [round(fl / (t / 1e3) / 1e12, 2) for t in per_mode],
-            "fp32_mfma_frac": [round(fl / (t / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4) for t in per_mode]}
+        Xin = P3 if dt == _abi.CPM_BF16X2 else X3
+        step_ms, per_mode = time_modes(torch, _abi, Xin, dims3, U3, outs, ws3, dt, 5, 1, stream)
+        fl = 2.0 * I3 * R
+        rec = {"ms_all_modes": round(step_ms, 3),
+               "per_mode_us": [round(t * 1e3, 1) for t in per_mode],
+               "per_mode_TFLOP/s": [round(fl / (t / 1e3) / 1e12, 2) for t in per_mode],
+               "per_mode_hbm_frac": [round(algo_bytes(dims3, R, n, 4) / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                     for n, t in enumerate(per_mode)]}
+        if dt == _abi.CPM_BF16X2:
+            # three bf16 MFMA products per multiply-add of the method
+            rec["per_mode_bf16_mfma_frac"] = [round(3 * fl / (t / 1e3) / 1e12 / BF16_PEAK_TFLOPS, 4)
+                                              for t in per_mode]
+        else:
+            rec["per_mode_fp32_peak_frac"] = [round(fl / (t / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4)
+                                              for t in per_mode]
+        runs[tag] = rec
+        out["sym4d_" + tag] = rec
         del U3, outs, ws3
-    del X3
+    out["sym4d_r128_split_bf16_speedup_over_fp32"] = {
+        "all_modes": round(runs["fp32_r128"]["ms_all_modes"] / runs["bf16x2_r128"]["ms_all_modes"], 3),
+        "per_mode": [round(a / b, 3) for a, b in zip(runs["fp32_r128"]["per_mode_us"],
+                                                       runs["bf16x2_r128"]["per_mode_us"])]}
+    del X3, P3
     torch.cuda.empty_cache()
 
-    # CP gradient evaluations per second on 64^5 (float32, R=32).
-    dims5, R5 = (64,) * 5, 32
-    X5, _ = inputs.noisy_low_rank(dims5, R5, seed_factors=9, seed_noise=10, eta=0.05, device="cuda")
-    U5 = inputs.normal_factors(dims5, R5, seed=11, device="cuda")
+    # CP gradient evaluations per second on 64^5: float32 and split bf16.
+    dims5 = (64,) * 5
+    X5, _ = inputs.noisy_low_rank(dims5, 32, seed_factors=9, seed_noise=10, eta=0.05, device="cuda")
+    P5 = _abi.split_bf16(X5.reshape(-1))
     x5 = float(_abi.xnorm2(X5, dims5).item())
-    ws5 = torch.empty(_abi.cp_grad_workspace_bytes(dims5, R5, _abi.CPM_F32), dtype=torch.uint8, device=dev)
-    grads = [torch.empty_like(u) for u in U5]
-    loss = torch.empty((), dtype=torch.float64, device=dev)
-    for _ in range(2):
-        _abi.cp_grad(X5, dims5, U5, grads=grads, xnorm2=x5, loss=loss, workspace=ws5)
-    reps = 5
-    t0 = timer.event()
-    for _ in range(reps):
-        _abi.cp_grad(X5, dims5, U5, grads=grads, xnorm2=x5, loss=loss, workspace=ws5)
-    t1 = timer.event()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
-    out["cp_grad_64p5_r32_fp32"] = {"ms_per_eval": round(ms, 3), "evals_per_s": round(1e3 / ms, 2),
-                                    "hbm_roofline_evals_per_s": round(HBM_PEAK_GBS * 1e9 / (5 * 4 * 64 ** 5), 1)}
-    del X5
+    for R5 in (32, 128):
+        U5 = inputs.normal_factors(dims5, R5, seed=11, device="cuda")
+        grads = [torch.empty_like(u) for u in U5]
+        loss = torch.empty((), dtype=torch.float64, device=dev)
+        res = {}
+        for dt, tag, Xin in [(_abi.CPM_F32, "fp32", X5), (_abi.CPM_BF16X2, "bf16x2", P5)]:
+            ws5 = torch.empty(_abi.cp_grad_workspace_bytes(dims5, R5, dt), dtype=torch.uint8, device=dev)
+            for _ in range(2):
+                _abi.cp_grad(Xin, dims5, U5, grads=grads, xnorm2=x5, loss=loss, dtype=dt, workspace=ws5)
+            reps = 5
+            t0 = timer.event()
+            for _ in range(reps):
+                _abi.cp_grad(Xin, dims5, U5, grads=grads, xnorm2=x5, loss=loss, dtype=dt, workspace=ws5)
+            t1 = timer.event()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / reps
+            res[tag] = ms
+            out["cp_grad_64p5_r%d_%s" % (R5, tag)] = {
+                "ms_per_eval": round(ms, 3), "evals_per_s": round(1e3 / ms, 2),
+                "hbm_roofline_evals_per_s": round(HBM_PEAK_GBS * 1e9 / (5 * 4 * 64 ** 5), 1)}
+            del ws5
+        out["cp_grad_64p5_r%d_split_bf16_speedup_over_fp32" % R5] = round(res["fp32"] / res["bf16x2"], 3)
+        del U5, grads
+    del X5, P5
     torch.cuda.empty_cache()
     return out
 
