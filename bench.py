@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="main workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 512 MiB device copy (known bytes) to scale HBM counters")
     return ap.parse_args()
 
 
@@ -157,6 +159,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+
+    if args.calibrate_copy:
+        # 512 MiB read + 512 MiB written per launch, three launches.
+        src = torch.randn(128 * 1024 * 1024, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---------------- main workload: 512^3 float32, R = 32 ----------------
     dims, R = (512, 512, 512), 32
