@@ -7,10 +7,12 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "../../include/cpmttkrp.h"
 #include "als_kernels.hpp"
 #include "bf16_kernels.hpp"
+#include "mttkrp32_kernels.hpp"
 #include "mttkrp_kernels.hpp"
 
 using namespace cpm;
@@ -74,12 +76,14 @@ cpm_status check_dtype(cpm_dtype dt) {
 // ---------------------------------------------------------------------------
 // Launch planning for one mode.
 // ---------------------------------------------------------------------------
-enum Kind { kLeft = 0, kRight = 1, kBf16Left = 2, kBf16Right = 3 };
+enum Kind { kLeft = 0, kRight = 1, kBf16Left = 2, kBf16Right = 3, kLeft32 = 4, kRight32 = 5 };
 
 struct Plan {
     Kind kind;
     int64_t IL, In, IR, J;
-    int NB, MB, ncb;          // n-blocks per column block, m-blocks (right: MJ), column blocks
+    int NB, MB, ncb;          // n-blocks per column block, m-blocks (right: MJ), column blocks;
+                              // 32x32 kernels: NB = 32-column blocks, MB = row groups (left) or
+                              // j-groups of waves (right), Q = j per lane (right)
     int p;                    // left: inner modes [0, p); right: inner modes [mode+1, p)
     int64_t G_in, G_out;      // inner rows of the contracted product; left: outer left extent
     int64_t n_outer;          // outer blocks
@@ -96,6 +100,7 @@ struct Plan {
 
 constexpr int kTargetGroups = 512;        // about two resident work-groups per CU
 constexpr size_t kTileBytes = 78 * 1024;   // LDS for the resident Khatri-Rao tile
+constexpr int64_t kMaxBufferOffset = 0xFFFFFF00LL;  // reach of one buffer resource
 
 int pow2_at_least(int v) {
     int p = 1;
@@ -167,6 +172,81 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
     p.partial_bytes = p.reduce ? (size_t)p.S * p.nlc * rows * R * 4 : 0;
 }
 
+// Float32 tiling on the 32x32 MFMA kernels (mttkrp32_kernels.hpp).
+// Left-first once the left product has 32 entries (and rows allow 16-byte
+// loads); right-first otherwise.  The inner part of the contracted index
+// is grown until it reaches the chunk length (a long inner range is then cut
+// into chunks).  Returns false when these kernels do not apply.
+constexpr int64_t kF32Chunk = 128;  // inner entries per work-group (tile of 16 KB per 32 columns)
+constexpr int kF32GroupsLeft = 768;   // three resident work-groups per CU
+constexpr int kF32GroupsRight = 512;  // two (its cross-wave reduction takes 16 KB of LDS per j)
+
+bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *X) {
+    const int nct = (R + 31) / 32;
+    const bool left = p.IL >= 32;
+    const int ncmax = left ? 4 : 2;
+    p.NB = nct <= ncmax ? pow2_at_least(nct) : ncmax;
+    p.ncb = (int)ceil_div(nct, p.NB);
+    const int RP = 32 * p.NB;
+    const uintptr_t xa = (uintptr_t)X;
+    if (left) {
+        p.kind = kLeft32;
+        int q = 0;
+        p.G_in = 1;
+        while (q < mode && p.G_in < kF32Chunk) p.G_in *= dims[q++];
+        if (p.G_in % 4 != 0 || xa % 16 != 0) return false;  // rows need 16-byte loads
+        p.p = q;
+        p.G_out = p.IL / p.G_in;
+        p.n_outer = p.G_out * p.IR;
+        p.MB = p.G_in >= 128 ? 1 : (p.G_in >= 64 ? 2 : 4);  // wave groups along rows
+        while (p.MB > 1 && 32 * p.MB / 2 >= p.In) p.MB /= 2;
+        const int64_t unit = (4 / p.MB) * 32;
+        p.LC = (int)std::max(unit, std::min(kF32Chunk / unit * unit, ceil_div(p.G_in, unit) * unit));
+        p.SPB = p.LC / (int)unit;
+        p.nlc = ceil_div(p.G_in, p.LC);
+        p.ntiles = ceil_div(p.In, 32 * p.MB);
+        p.lds = std::max((size_t)4 * RP * (p.LC + 4) + 16384, (size_t)16384 * p.NB);
+        p.v4 = true;
+        p.max_offset = (31 * p.IL + p.LC + 4) * 4;
+        p.J = p.In;
+    } else {
+        p.kind = kRight32;
+        p.J = p.In * p.IL;
+        const bool a4 = p.J % 4 == 0 && xa % 16 == 0, a2 = p.J % 2 == 0 && xa % 8 == 0;
+        // Waves split the rows of a narrow j tile: the partial result of a
+        // work-group (its j tile x R) stays small next to the X it streams.
+        int tj = 1;
+        const int wj = 1;
+        if (p.NB == 1 && a4 && p.J >= 128) tj = 4;
+        else if (a2 && p.J >= 64) tj = 2;
+        p.Q = tj;
+        p.MB = wj;
+        const int64_t unit = 8 * (4 / wj);
+        const int64_t lcap = kF32Chunk;
+        int q = mode + 1;
+        p.G_in = 1;
+        while (q < N && p.G_in < lcap) p.G_in *= dims[q++];
+        p.p = q;
+        p.n_outer = p.IR / p.G_in;
+        const int64_t lcmax = std::max<int64_t>(unit, lcap / unit * unit);
+        p.LC = (int)std::min<int64_t>(lcmax, ceil_div(p.G_in, unit) * unit);
+        p.SPB = p.LC / (int)unit;
+        p.nlc = ceil_div(p.G_in, p.LC);
+        p.ntiles = ceil_div(p.J, 32 * tj * wj);
+        p.lds = std::max((size_t)4 * RP * (p.LC + 4), wj < 4 ? (size_t)16384 * tj * p.NB : (size_t)0);
+        p.v4 = tj > 1;
+        p.max_offset = ((int64_t)p.LC * p.J + 32 * tj + 4) * 4;
+    }
+    const int64_t groups = p.kind == kLeft32 ? kF32GroupsLeft : kF32GroupsRight;
+    int64_t S = std::max<int64_t>(1, ceil_div(groups, p.ntiles * p.nlc * p.ncb));
+    S = std::min(S, p.n_outer);
+    p.bps = ceil_div(p.n_outer, S);
+    p.S = ceil_div(p.n_outer, p.bps);
+    p.reduce = p.S * p.nlc > 1 || (p.kind == kRight32 && mode > 0);
+    p.partial_bytes = p.reduce ? (size_t)p.S * p.nlc * (p.kind == kLeft32 ? p.In : p.J) * R * 4 : 0;
+    return true;
+}
+
 Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const void *X) {
     Plan p{};
     p.IL = 1;
@@ -181,12 +261,18 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
         plan_bf16(p, dims, N, R, mode, X);
         return p;
     }
+    if (dt == CPM_F32) {
+        Plan q = p;
+        if (plan_f32(q, dims, N, R, mode, X) && q.max_offset < kMaxBufferOffset) return q;
+    }
     const bool left = p.IL >= 16;
     const bool dbl = dt == CPM_F64;
     // n-blocks (16 rank columns) per work-group; wider ranks take several
     // column blocks.  The right-first kernel keeps four accumulator rows per
     // lane, so it stays at two blocks.
-    const int nbmax = left ? (dbl ? 2 : 8) : (dbl ? 1 : 2);
+    // (float reaches this tiling only as the fallback of the 32x32 kernels:
+    // misaligned rows or offsets beyond one buffer resource)
+    const int nbmax = left ? 2 : (dbl ? 1 : 2);
     int nb = RPtot / 16;
     if (nb <= nbmax) {
         p.NB = pow2_at_least(nb);
@@ -210,12 +296,12 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
     };
     if (left) {
         p.kind = kLeft;
-        p.MB = (p.NB >= 8 || (dbl && p.NB >= 2)) ? 1 : 2;
+        p.MB = (!dbl || p.NB >= 2) ? 1 : 2;
         while (p.MB > 1 && 16 * p.MB / 2 >= p.In) p.MB /= 2;
         p.p = pick_inner(0, mode, p.G_in);
         p.G_out = p.IL / p.G_in;
         p.n_outer = p.G_out * p.IR;
-        p.Q = (p.G_in > 64) ? 2 : 1;  // 128-byte row bursts once rows are long enough
+        p.Q = (dbl && p.G_in > 64) ? 2 : 1;  // 128-byte row bursts once rows are long enough
         const int64_t unit = 64 * p.Q;
         p.LC = (int)std::min<int64_t>(lcmax / unit * unit, ceil_div(p.G_in, unit) * unit);
         p.SPB = p.LC / (int)unit;
@@ -235,7 +321,7 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
     } else {
         p.kind = kRight;
         p.J = p.In * p.IL;
-        p.MB = (dbl || p.NB > 1 || p.J <= 64) ? 1 : 2;  // MJ
+        p.MB = 1;  // MJ
         p.p = pick_inner(mode + 1, N, p.G_in);
         p.n_outer = p.IR / p.G_in;
         p.LC = (int)std::min<int64_t>(lcmax, ceil_div(p.G_in, 64) * 64);
@@ -289,12 +375,8 @@ void launch_left(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &kou
 template <>
 void launch_left<float>(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
                         float *partial, hipStream_t st) {
-    switch (p.NB) {
-    case 1: launch_left_m<float, 1>(p, X, kin, kout, R, partial, st); break;
-    case 2: launch_left_m<float, 2>(p, X, kin, kout, R, partial, st); break;
-    case 4: launch_left_m<float, 4>(p, X, kin, kout, R, partial, st); break;
-    default: launch_left_q<float, 8, 1>(p, X, kin, kout, R, partial, st); break;
-    }
+    if (p.NB == 1) launch_left_t<float, 1, 1, 1>(p, X, kin, kout, R, partial, st);
+    else launch_left_t<float, 2, 1, 1>(p, X, kin, kout, R, partial, st);
 }
 template <>
 void launch_left<double>(const Plan &p, const double *X, const Krp<double> &kin, const Krp<double> &kout, int R,
@@ -321,18 +403,57 @@ void launch_right(const Plan &p, const T *X, const Krp<T> &kin, const Krp<T> &ko
 template <>
 void launch_right<float>(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
                          float *partial, hipStream_t st) {
-    if (p.NB == 1) {
-        if (p.MB == 2) launch_right_t<float, 1, 2>(p, X, kin, kout, R, partial, st);
-        else launch_right_t<float, 1, 1>(p, X, kin, kout, R, partial, st);
-    } else {
-        launch_right_t<float, 2, 1>(p, X, kin, kout, R, partial, st);
-    }
+    if (p.NB == 1) launch_right_t<float, 1, 1>(p, X, kin, kout, R, partial, st);
+    else launch_right_t<float, 2, 1>(p, X, kin, kout, R, partial, st);
 }
 template <>
 void launch_right<double>(const Plan &p, const double *X, const Krp<double> &kin, const Krp<double> &kout, int R,
                           double *partial, hipStream_t st) {
     launch_right_t<double, 1, 1>(p, X, kin, kout, R, partial, st);
     (void)p;
+}
+
+template <int NC, int WM>
+void launch_left32_t(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
+                     float *partial, hipStream_t st) {
+    dim3 grid((unsigned)p.ntiles, (unsigned)(p.S * p.nlc), (unsigned)p.ncb);
+    hipLaunchKernelGGL((k_left32<NC, WM>), grid, dim3(kThreads), p.lds, st, X, p.G_in, p.G_out, p.In, p.n_outer, kin,
+                       kout, R, p.SPB, p.nlc, p.bps, partial);
+}
+
+template <int NC>
+void launch_left32_m(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
+                     float *partial, hipStream_t st) {
+    if (p.MB == 4) launch_left32_t<NC, 4>(p, X, kin, kout, R, partial, st);
+    else if (p.MB == 2) launch_left32_t<NC, 2>(p, X, kin, kout, R, partial, st);
+    else launch_left32_t<NC, 1>(p, X, kin, kout, R, partial, st);
+}
+
+void launch_left32(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
+                   float *partial, hipStream_t st) {
+    if (p.NB == 1) launch_left32_m<1>(p, X, kin, kout, R, partial, st);
+    else if (p.NB == 2) launch_left32_m<2>(p, X, kin, kout, R, partial, st);
+    else launch_left32_m<4>(p, X, kin, kout, R, partial, st);
+}
+
+template <int NC, int TJ, int WJ>
+void launch_right32_t(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
+                      float *partial, hipStream_t st) {
+    dim3 grid((unsigned)p.ntiles, (unsigned)(p.S * p.nlc), (unsigned)p.ncb);
+    hipLaunchKernelGGL((k_right32<NC, TJ, WJ>), grid, dim3(kThreads), p.lds, st, X, p.J, p.G_in, p.n_outer, kin,
+                       kout, R, p.SPB, p.nlc, p.bps, partial);
+}
+
+void launch_right32(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
+                    float *partial, hipStream_t st) {
+    if (p.NB == 1) {
+        if (p.Q == 4) launch_right32_t<1, 4, 1>(p, X, kin, kout, R, partial, st);
+        else if (p.Q == 2) launch_right32_t<1, 2, 1>(p, X, kin, kout, R, partial, st);
+        else launch_right32_t<1, 1, 1>(p, X, kin, kout, R, partial, st);
+    } else {
+        if (p.Q == 2) launch_right32_t<2, 2, 1>(p, X, kin, kout, R, partial, st);
+        else launch_right32_t<2, 1, 1>(p, X, kin, kout, R, partial, st);
+    }
 }
 
 // Enqueue one MTTKRP (arguments already validated).
@@ -360,7 +481,8 @@ cpm_status run_mttkrp_t(const Plan &p, const void *Xv, const int64_t *dims, int 
     int in_modes[CPM_MAX_MODES], out_modes[CPM_MAX_MODES], left_modes[CPM_MAX_MODES];
     int nin = 0, nout = 0, nleft = 0;
     for (int k = 0; k < mode; ++k) left_modes[nleft++] = k;
-    if (p.kind == kLeft) {
+    const bool lf = p.kind == kLeft || p.kind == kLeft32;
+    if (lf) {
         for (int k = 0; k < p.p; ++k) in_modes[nin++] = k;
         for (int k = p.p; k < mode; ++k) out_modes[nout++] = k;
         for (int k = mode + 1; k < N; ++k) out_modes[nout++] = k;
@@ -373,19 +495,28 @@ cpm_status run_mttkrp_t(const Plan &p, const void *Xv, const int64_t *dims, int 
     const T *X = reinterpret_cast<const T *>(Xv);
     T *out = reinterpret_cast<T *>(outv);
     T *partial = p.reduce ? reinterpret_cast<T *>(ws) : out;
+    if constexpr (std::is_same<T, float>::value) {
+        if (p.kind == kLeft32) {
+            launch_left32(p, X, kin, kout, R, partial, st);
+            LAUNCH_CHECK("k_left32");
+        } else if (p.kind == kRight32) {
+            launch_right32(p, X, kin, kout, R, partial, st);
+            LAUNCH_CHECK("k_right32");
+        }
+    }
     if (p.kind == kLeft) {
         launch_left<T>(p, X, kin, kout, R, partial, st);
         LAUNCH_CHECK("k_contract_left");
-    } else {
+    } else if (p.kind == kRight) {
         launch_right<T>(p, X, kin, kout, R, partial, st);
         LAUNCH_CHECK("k_contract_right");
     }
     if (p.reduce) {
         const int64_t total = p.In * R;
-        const int64_t rows_per_slice = (p.kind == kLeft) ? p.In : p.J;
+        const int64_t rows_per_slice = lf ? p.In : p.J;
         // right-first for mode > 0: the multi-TTV with K_L (all left modes)
-        Krp<T> kred = krp_of<T>(factors, dims, left_modes, p.kind == kLeft ? 0 : nleft);
-        const int64_t il = (p.kind == kLeft) ? 1 : p.IL;
+        Krp<T> kred = krp_of<T>(factors, dims, left_modes, lf ? 0 : nleft);
+        const int64_t il = lf ? 1 : p.IL;
         hipLaunchKernelGGL((k_reduce<T, T>), dim3((unsigned)ceil_div(total, 64)), dim3(kThreads), 0, st, partial,
                            p.S * p.nlc, rows_per_slice, p.In, il, kred, R, out);
         LAUNCH_CHECK("k_reduce");
@@ -502,10 +633,21 @@ cpm_status validate_mttkrp(const void *X, const int64_t *dims, int N, const void
 }
 
 size_t mttkrp_ws(const int64_t *dims, int N, int R, int mode, cpm_dtype dt) {
-    // The vector-load choice depends on X's alignment, not the sizes; plan
-    // with an aligned pointer (partial sizes do not depend on it).
-    Plan p = make_plan(dims, N, R, mode, dt, (const void *)(uintptr_t)4096);
-    return align_up(p.partial_bytes);
+    // The tiling may depend on X's alignment (vector width of the loads);
+    // size the workspace for every alignment a caller can pass.
+    size_t b = 0;
+    for (uintptr_t a : {(uintptr_t)4096, (uintptr_t)8, (uintptr_t)4, (uintptr_t)2})
+        b = std::max(b, make_plan(dims, N, R, mode, dt, (const void *)a).partial_bytes);
+    return align_up(b);
+}
+
+// Every mode's tiling must keep its buffer-load offsets within one resource.
+cpm_status check_reach(const void *X, const int64_t *dims, int N, int R, cpm_dtype dt) {
+    for (int n = 0; n < N; ++n)
+        if (make_plan(dims, N, R, n, dt, X).max_offset >= kMaxBufferOffset)
+            return fail(CPM_EUNSUPPORTED, "mode %d: rows of the tensor are too far apart for one buffer resource "
+                        "(4 GiB reach)", n);
+    return CPM_OK;
 }
 
 size_t max_mttkrp_ws(const int64_t *dims, int N, int R, cpm_dtype dt) {
@@ -642,7 +784,7 @@ cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *
     cpm_status s = validate_mttkrp(X, dims, N, factors, R, mode, out, dt, &total);
     if (s) return s;
     Plan p = make_plan(dims, N, R, mode, dt, X);
-    if (p.max_offset >= (int64_t)0xFFFFFF00LL)
+    if (p.max_offset >= kMaxBufferOffset)
         return fail(CPM_EUNSUPPORTED, "mode %d: entries %lld apart along mode %d exceed the 4 GiB reach of one "
                     "buffer resource", mode, (long long)p.IL, mode);
     const size_t need = align_up(p.partial_bytes);
@@ -685,6 +827,8 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
     const size_t need = layout_solve(dims, N, R, dt, nullptr, true).need;
     if (!workspace || ws_bytes < need)
         return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    s = check_reach(X, dims, N, R, dt);
+    if (s) return s;
     s = check_lds_for_cholesky(R);
     if (s) return s;
     SolveWs w = layout_solve(dims, N, R, dt, (char *)workspace, true);
@@ -777,6 +921,8 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
     const size_t need = layout_solve(dims, N, R, dt, nullptr, false).need;
     if (!workspace || ws_bytes < need)
         return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    s = check_reach(X, dims, N, R, dt);
+    if (s) return s;
     SolveWs w = layout_solve(dims, N, R, dt, (char *)workspace, false);
     for (int k = 0; k < N; ++k) {
         s = gram(factors[k], dims[k], R, dt, w.gpart, w.grams + (size_t)k * R * R, stream);

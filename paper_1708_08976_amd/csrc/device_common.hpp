@@ -339,11 +339,12 @@ struct KrpCursor {
     }
 };
 
-// Raw factor values of one row of a Khatri-Rao product for NB lane columns,
-// fetched ahead of use (first ZS factors) and multiplied when needed.  The
-// row index is the same in every lane, so the index arithmetic is scalar;
-// the loads are unconditional buffer loads (a column past R reads zero).
-template <typename T, int NB>
+// Raw factor values of one row of a Khatri-Rao product for NB lane columns
+// (cbase, cbase + CS, ...), fetched ahead of use (first ZS factors) and
+// multiplied when needed.  The row index is the same in every lane, so the
+// index arithmetic is scalar; the loads are unconditional buffer loads (a
+// column past R reads zero).
+template <typename T, int NB, int CS = 16>
 struct KrpRowVals {
     static constexpr int ZS = kCursorZ;
     T f[NB][ZS];
@@ -358,14 +359,14 @@ struct KrpRowVals {
             const int64_t rowz = (z < k.Z) ? cur.d[z] : 0;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const int c = cbase + 16 * nb;
+                const int c = cbase + CS * nb;
                 const uint32_t off = (c < R) ? (uint32_t)((rowz * R + c) * (int64_t)sizeof(T)) : kNoLoad;
                 f[nb][z] = buf_load1(rs, off, T(0));  // not touched until value(): no wait here
             }
         }
     }
     __device__ inline T value(const Krp<T> &k, int R, int cbase, int nb) const {
-        const int c = cbase + 16 * nb;
+        const int c = cbase + CS * nb;
         if (c >= R) return T(0);
         T v = f[nb][0];
 #pragma unroll
@@ -383,6 +384,14 @@ struct KrpRowVals {
 // (measured on gfx950).  16x16x32 bf16: lane l holds A[l%16][8*(l/16)+e]
 // and B[8*(l/16)+e][l%16] for e = 0..7, accumulator as for f32.
 // ---------------------------------------------------------------------------
+// 32x32x2 f32: lane l holds A[l%32][l/32] and B[l/32][l%32]; accumulator
+// element j (0..15) of lane l holds D[acc32_row(l, j)][l%32].
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+__device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ inline int acc32_row(int lane, int j) { return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3); }
+
 template <typename T> __device__ inline int acc_row(int lane, int j);
 template <> __device__ inline int acc_row<float>(int lane, int j) { return 4 * (lane >> 4) + j; }
 template <> __device__ inline int acc_row<double>(int lane, int j) { return 4 * j + (lane >> 4); }
