@@ -205,7 +205,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.SPB = p.LC / (int)unit;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.In, 32 * p.MB);
-        p.lds = std::max((size_t)4 * RP * (p.LC + 4) + 16384, (size_t)16384 * p.NB);
+        p.lds = std::max((size_t)4 * RP * (p.LC + 4) + 16384 + (size_t)4 * kScaleBlocks * RP, (size_t)16384 * p.NB);
         p.v4 = true;
         p.max_offset = (31 * p.IL + p.LC + 4) * 4;
         p.J = p.In;
@@ -233,7 +233,8 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.SPB = p.LC / (int)unit;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.J, 32 * tj * wj);
-        p.lds = std::max((size_t)4 * RP * (p.LC + 4), wj < 4 ? (size_t)16384 * tj * p.NB : (size_t)0);
+        p.lds = std::max((size_t)4 * RP * (p.LC + 4) + (size_t)4 * kScaleBlocks * RP,
+                         wj < 4 ? (size_t)16384 * tj * p.NB : (size_t)0);
         p.v4 = tj > 1;
         p.max_offset = ((int64_t)p.LC * p.J + 32 * tj + 4) * 4;
     }

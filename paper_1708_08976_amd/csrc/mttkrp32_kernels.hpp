@@ -17,7 +17,8 @@
 //   * the outer scale S(o, c) of the current block multiplies the B
 //     operands as they leave LDS, so the MFMA accumulates full Khatri-Rao
 //     values K_in(g, c) * S(o, c) directly: one accumulator set, no
-//     per-block epilogue.
+//     per-block epilogue.  The scales of the coming blocks sit in an LDS
+//     table (fill_scales), so reading them never waits behind X loads.
 #pragma once
 
 #include "device_common.hpp"
@@ -45,6 +46,24 @@ namespace cpm {
 //   grid.x = row tile (32*WM rows), grid.y = lc + nlc*split, grid.z = column
 //   block.  partial: [gridDim.y][In][R].
 // ---------------------------------------------------------------------------
+// Outer scales S(o, c) of up to kScaleBlocks consecutive blocks, for the
+// work-group's rank columns, held in LDS ([block][RP]).  The stream runs in
+// chunks of kScaleBlocks blocks; the table is refilled between chunks (a
+// barrier and one round of factor loads), outside the unrolled step loop.
+// Reading a scale in the stream is an LDS access, so it never waits on the
+// in-order completion counter of the X loads in flight.  kScaleBlocks is a
+// multiple of the register ring (3), so every chunk starts on ring slot 0.
+constexpr int kScaleBlocks = 48;
+template <int RP>
+__device__ inline void fill_scales(const Krp<float> &kout, int R, int c0, int64_t ob, int64_t o_end, float *stab) {
+    if (kout.Z == 0) {
+        for (int e = threadIdx.x; e < kScaleBlocks * RP; e += kThreads) stab[e] = 1.f;
+        return;
+    }
+    build_tile_batched<float, RP, 8>(kout, R, c0, ob, kScaleBlocks, o_end,
+                                     [&](int q, int c, float v) { stab[q * RP + c] = v; });
+}
+
 template <int NC, int WM, int RING = 3>
 __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X, int64_t IL_in, int64_t IL_out,
                                                      int64_t In, int64_t n_outer, Krp<float> kin,
@@ -117,31 +136,19 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
     for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
     build_tile_batched<float, RP, 16>(kin, R, c0, l0, LC, IL_in, [&](int q, int c, float v) { tile[c * PT + q] = v; });
 
-    // Outer scale of the current block (S(o, c) for the lane's columns) and
-    // the raw factor values of the next block, loaded one block ahead.
-    int64_t co = o_begin;
+    float *stab = stg + (4 - wave) * 32 * WS;  // [kScaleBlocks][RP], after the four staging slots
+    fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
+    int64_t co = o_begin, tb0 = o_begin;
     int cs = 0;
-    const int cb = c0 + m;
-    KrpRowVals<float, NC, 32> sv;
-    KrpCursor<float> scur;
     float scl[NC];
-#pragma unroll
-    for (int nc = 0; nc < NC; ++nc) scl[nc] = 1.f;
-    if (has_out && o_begin < o_end) {
-        scur.set(kout, o_begin);
-        sv.fetch(kout, R, cb, scur);
-#pragma unroll
-        for (int nc = 0; nc < NC; ++nc) scl[nc] = sv.value(kout, R, cb, nc);
-        if (o_begin + 1 < o_end) {
-            scur.next(kout);
-            sv.fetch(kout, R, cb, scur);
-        }
-    }
     f32x16 acc[NC];
 #pragma unroll
     for (int nc = 0; nc < NC; ++nc) acc[nc] = f32x16{};
     const float *tb = tile + m * PT + wl + 4 * h;
-    __syncthreads();
+    auto load_scales = [&]() {
+#pragma unroll
+        for (int nc = 0; nc < NC; ++nc) scl[nc] = stab[(co - tb0) * RP + 32 * nc + m];
+    };
 
     auto compute_step = [&](const f32x4 (&xl)[4]) {
 #pragma unroll
@@ -165,30 +172,33 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
                 for (int nc = 0; nc < NC; ++nc) acc[nc] = mfma32(a[q][t], b[nc][q][t], acc[nc]);
         if (++cs == SPB) {
             cs = 0;
-            ++co;
-            if (has_out && co < o_end) {
-#pragma unroll
-                for (int nc = 0; nc < NC; ++nc) scl[nc] = sv.value(kout, R, cb, nc);
-                if (co + 1 < o_end) {
-                    scur.next(kout);
-                    sv.fetch(kout, R, cb, scur);
-                }
-            }
+            if (++co - tb0 < kScaleBlocks && co < o_end) load_scales();
         }
     };
 
-    const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
-    int64_t st = 0;
-    for (; st + RING <= nsteps; st += RING) {
+    // Chunks of kScaleBlocks blocks; within a chunk RING steps per pass with
+    // compile-time ring slots.
+    for (; tb0 < o_end; tb0 += kScaleBlocks) {
+        if (tb0 != o_begin) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
+        __syncthreads();
+        co = tb0;
+        load_scales();
+        const int64_t nsteps = (min(o_end, tb0 + kScaleBlocks) - tb0) * SPB;
+        int64_t st = 0;
+        for (; st + RING <= nsteps; st += RING) {
 #pragma unroll
-        for (int k = 0; k < RING; ++k) {
-            load_step(x[(k + RING - 1) % RING]);
-            compute_step(x[k]);
+            for (int k = 0; k < RING; ++k) {
+                load_step(x[(k + RING - 1) % RING]);
+                compute_step(x[k]);
+            }
         }
-    }
+        // only the last chunk can end off a RING boundary; its remaining
+        // steps are already in slots 0 .. RING - 2
 #pragma unroll
-    for (int k = 0; k < RING - 1; ++k)
-        if (st + k < nsteps) compute_step(x[k]);
+        for (int k = 0; k < RING - 1; ++k)
+            if (st + k < nsteps) compute_step(x[k]);
+        __syncthreads();  // every wave is done with this chunk's scales
+    }
 
     // Sum the WC waves that share rows, in wave order, and store.
     __syncthreads();
@@ -308,31 +318,21 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
     for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
     build_tile_batched<float, RP, 16>(kin, R, c0, r0, LC, IR_in, [&](int q, int c, float v) { tile[c * PT + q] = v; });
 
-    int64_t co = o_begin;
+    float *stab = tile + RP * PT;  // [kScaleBlocks][RP]
+    fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
+    int64_t co = o_begin, tb0 = o_begin;
     int cs = 0;
-    const int cb = c0 + m;
-    KrpRowVals<float, NC, 32> sv;
-    KrpCursor<float> scur;
     float scl[NC];
-#pragma unroll
-    for (int nc = 0; nc < NC; ++nc) scl[nc] = 1.f;
-    if (has_out && o_begin < o_end) {
-        scur.set(kout, o_begin);
-        sv.fetch(kout, R, cb, scur);
-#pragma unroll
-        for (int nc = 0; nc < NC; ++nc) scl[nc] = sv.value(kout, R, cb, nc);
-        if (o_begin + 1 < o_end) {
-            scur.next(kout);
-            sv.fetch(kout, R, cb, scur);
-        }
-    }
     f32x16 acc[TJ][NC];
 #pragma unroll
     for (int t = 0; t < TJ; ++t)
 #pragma unroll
         for (int nc = 0; nc < NC; ++nc) acc[t][nc] = f32x16{};
     const float *tb = tile + m * PT + wrow + 4 * h;
-    __syncthreads();
+    auto load_scales = [&]() {
+#pragma unroll
+        for (int nc = 0; nc < NC; ++nc) scl[nc] = stab[(co - tb0) * RP + 32 * nc + m];
+    };
 
     auto compute_step = [&](const jv (&a)[4]) {
         f32x4 b[NC];
@@ -347,30 +347,29 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
                 for (int nc = 0; nc < NC; ++nc) acc[t][nc] = mfma32(jcomp<TJ>(a[s], t), b[nc][s], acc[t][nc]);
         if (++cs == SPB) {
             cs = 0;
-            ++co;
-            if (has_out && co < o_end) {
-#pragma unroll
-                for (int nc = 0; nc < NC; ++nc) scl[nc] = sv.value(kout, R, cb, nc);
-                if (co + 1 < o_end) {
-                    scur.next(kout);
-                    sv.fetch(kout, R, cb, scur);
-                }
-            }
+            if (++co - tb0 < kScaleBlocks && co < o_end) load_scales();
         }
     };
 
-    const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
-    int64_t st = 0;
-    for (; st + RING <= nsteps; st += RING) {
+    for (; tb0 < o_end; tb0 += kScaleBlocks) {
+        if (tb0 != o_begin) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
+        __syncthreads();
+        co = tb0;
+        load_scales();
+        const int64_t nsteps = (min(o_end, tb0 + kScaleBlocks) - tb0) * SPB;
+        int64_t st = 0;
+        for (; st + RING <= nsteps; st += RING) {
 #pragma unroll
-        for (int k = 0; k < RING; ++k) {
-            load_step(x[(k + RING - 1) % RING]);
-            compute_step(x[k]);
+            for (int k = 0; k < RING; ++k) {
+                load_step(x[(k + RING - 1) % RING]);
+                compute_step(x[k]);
+            }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < RING - 1; ++k)
-        if (st + k < nsteps) compute_step(x[k]);
+        for (int k = 0; k < RING - 1; ++k)
+            if (st + k < nsteps) compute_step(x[k]);
+        __syncthreads();
+    }
 
     auto store = [&](int64_t jrow, int c, float v) {
         if (jrow < J && c < R) partial[((int64_t)blockIdx.y * J + jrow) * R + c] = v;
