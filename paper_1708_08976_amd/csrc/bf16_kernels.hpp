@@ -49,20 +49,23 @@ __device__ inline f32x4 buf_load_raw16_scalar(rsrc_t r, uint32_t off, int64_t l,
 // (Kt[c][l]) so the B operand of a k-step is one 16-byte LDS read.
 // partial: [gridDim.y][In][R] float32.
 // ---------------------------------------------------------------------------
-template <int NB, int MB, int Q, bool V8, int RING = 3>
+template <int NB, int MB, int Q, bool V8, int WM = 1, int RING = 3>
 __global__ __launch_bounds__(kThreads) void k_contract_left_bf16(
     const uint16_t *__restrict__ Xp, int64_t I, int64_t IL_in, int64_t IL_out, int64_t In, int64_t n_outer,
     Krp<float> kin, Krp<float> kout, int R, int SPB, int64_t nlc, int64_t blocks_per_split,
     float *__restrict__ partial) {
     constexpr int RP = NB * 16;
+    constexpr int WC = 4 / WM;  // waves along the chunk; WM wave groups take separate row tiles
     const int WS = 32 * Q;
-    const int LC = 4 * WS * SPB;
+    const int LC = WC * WS * SPB;
     const int LCP = LC + 8;  // bf16 row pitch of the transposed tile (16-byte pad)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     uint16_t *kth = reinterpret_cast<uint16_t *>(smem_raw);
     uint16_t *ktl = kth + RP * LCP;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WC, wc = wave % WC;
     const int m = lane & 15, kg = lane >> 4;
     const int c0 = blockIdx.z * RP;
     const int64_t lc = blockIdx.y % nlc;
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_contract_left_bf16(
     const int64_t l0 = lc * LC;
     const int64_t lend = min(IL_in, l0 + LC);
     const int64_t IL = IL_in * IL_out;
-    const int64_t row_base = (int64_t)blockIdx.x * 16 * MB;
+    const int64_t row_base = (int64_t)blockIdx.x * 16 * MB * WM + 16 * MB * wm;  // this wave's rows
     const int64_t o_begin = split * blocks_per_split;
     const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
     const bool has_out = kout.Z > 0;
@@ -83,41 +86,51 @@ __global__ __launch_bounds__(kThreads) void k_contract_left_bf16(
             acc[mb][nb] = f32x4{0, 0, 0, 0};
             tot[mb][nb] = f32x4{0, 0, 0, 0};
         }
-    bool rok[MB];
+    // Descriptors over each 16-row block of the current outer block: rows
+    // past In lie outside the record count, and everything does once the
+    // split's blocks are exhausted; only a ragged last chunk needs a
+    // per-lane check.
+    int64_t rows_valid[MB];
+    uint32_t rec[MB];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) rok[mb] = row_base + 16 * mb + m < In;
+    for (int mb = 0; mb < MB; ++mb) {
+        rows_valid[mb] = max((int64_t)0, min((int64_t)16, In - row_base - 16 * mb));
+        rec[mb] = rows_valid[mb] == 16 ? kRsrcRange : (uint32_t)(rows_valid[mb] * IL * 2);
+    }
+    const bool ragged = lend - l0 < LC;
     const uint32_t lane_row = (uint32_t)(m * IL);
-    const int64_t lane_l = l0 + wave * WS * SPB + 8 * kg;
+    const int64_t lane_l = l0 + wc * WS * SPB + 8 * kg;
 
     int64_t cur_r = o_begin / IL_out, cur_h = o_begin - (o_begin / IL_out) * IL_out;
+    int64_t lo = o_begin;
     rsrc_t rh[MB], rl[MB];
     auto set_block = [&]() {
         const int64_t b = cur_r * In * IL + cur_h * IL_in;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-            const int64_t e = b + (row_base + 16 * mb) * IL;
-            rh[mb] = make_rsrc(Xp + e, kRsrcRange);
-            rl[mb] = make_rsrc(Xp + I + e, kRsrcRange);
+            const bool live = lo < o_end && rows_valid[mb] > 0;
+            const int64_t e = live ? b + (row_base + 16 * mb) * IL : 0;
+            rh[mb] = make_rsrc(Xp + e, live ? rec[mb] : 0u);
+            rl[mb] = make_rsrc(Xp + I + e, live ? rec[mb] : 0u);
         }
     };
     set_block();
 
-    int64_t lo = o_begin;
     int ls = 0;
     // a[mb][q][0] = hi, a[mb][q][1] = lo
     auto load_step = [&](f32x4 (&a)[MB][Q][2]) {
-        const bool live = lo < o_end;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int64_t l = lane_l + WS * ls + 32 * q;
-                const bool ok = live && rok[mb] && l < lend;
-                const uint32_t off = ok ? (uint32_t)((lane_row + l) * 2) : kNoLoad;
+                uint32_t off = (uint32_t)((lane_row + l) * 2);
                 if (V8) {
+                    if (ragged) off = l < lend ? off : kNoLoad;
                     a[mb][q][0] = buf_load_raw16(rh[mb], off);
                     a[mb][q][1] = buf_load_raw16(rl[mb], off);
                 } else {
+                    if (l >= lend) off = kNoLoad;
                     a[mb][q][0] = buf_load_raw16_scalar(rh[mb], off, l, lend);
                     a[mb][q][1] = buf_load_raw16_scalar(rl[mb], off, l, lend);
                 }
@@ -144,18 +157,13 @@ __global__ __launch_bounds__(kThreads) void k_contract_left_bf16(
         ktl[c * LCP + q] = bf16_rne_bits(v - bf16_bits_to_float(h));
     });
 
-    int64_t co = o_begin;
+    float *stab = reinterpret_cast<float *>(ktl + RP * LCP);  // [scale_blocks<RP>()][RP] outer scales
+    if (has_out) fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
+    int64_t co = o_begin, tb0 = o_begin;
     int cs = 0;
-    KrpRowVals<float, NB> sv;
-    KrpCursor<float> scur;
-    if (has_out && o_begin < o_end) {
-        scur.set(kout, o_begin);
-        sv.fetch(kout, R, c0 + m, scur);
-    }
-    __syncthreads();
 
     auto compute_step = [&](const f32x4 (&a)[MB][Q][2]) {
-        const int kbase = wave * WS * SPB + WS * cs + 8 * kg;
+        const int kbase = wc * WS * SPB + WS * cs + 8 * kg;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
 #pragma unroll
@@ -178,34 +186,37 @@ __global__ __launch_bounds__(kThreads) void k_contract_left_bf16(
             if (has_out) {
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const float s = sv.value(kout, R, c0 + m, nb);
+                    const float sc = stab[(co - tb0) * RP + 16 * nb + m];
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb) {
-                        tot[mb][nb] += acc[mb][nb] * s;
+                        tot[mb][nb] += acc[mb][nb] * sc;
                         acc[mb][nb] = f32x4{0, 0, 0, 0};
                     }
-                }
-                if (co + 1 < o_end) {
-                    scur.next(kout);
-                    sv.fetch(kout, R, c0 + m, scur);
                 }
             }
             ++co;
         }
     };
 
-    const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
-    int64_t st = 0;
-    for (; st + RING <= nsteps; st += RING) {
+    // Chunks of scale_blocks<RP>() blocks (a multiple of RING); the scale table is
+    // refilled between chunks, outside the unrolled step loop.
+    for (; tb0 < o_end; tb0 += scale_blocks<RP>()) {
+        if (tb0 != o_begin && has_out) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
+        __syncthreads();
+        const int64_t nsteps = (min(o_end, tb0 + scale_blocks<RP>()) - tb0) * SPB;
+        int64_t st = 0;
+        for (; st + RING <= nsteps; st += RING) {
 #pragma unroll
-        for (int k = 0; k < RING; ++k) {
-            load_step(x[(k + RING - 1) % RING]);
-            compute_step(x[k]);
+            for (int k = 0; k < RING; ++k) {
+                load_step(x[(k + RING - 1) % RING]);
+                compute_step(x[k]);
+            }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < RING - 1; ++k)
-        if (st + k < nsteps) compute_step(x[k]);
+        for (int k = 0; k < RING - 1; ++k)
+            if (st + k < nsteps) compute_step(x[k]);
+        __syncthreads();
+    }
     if (!has_out) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -224,11 +235,15 @@ __global__ __launch_bounds__(kThreads) void k_contract_left_bf16(
                 red[(((wave * MB + mb) * NB + nb) * 4 + j) * 64 + lane] = tot[mb][nb][j];
     __syncthreads();
     constexpr int PER_WAVE = MB * NB * 4 * 64;
-    for (int e = tid; e < PER_WAVE; e += kThreads) {
-        const int ln = e & 63, j = (e >> 6) & 3, blk = e >> 8;
+    for (int e = tid; e < WM * PER_WAVE; e += kThreads) {
+        const int g = e / PER_WAVE, r = e % PER_WAVE;  // row group, element
+        const int ln = r & 63, j = (r >> 6) & 3, blk = r >> 8;
         const int nb = blk % NB, mb = blk / NB;
-        const float sum = ((red[e] + red[PER_WAVE + e]) + red[2 * PER_WAVE + e]) + red[3 * PER_WAVE + e];
-        const int64_t row = row_base + 16 * mb + acc_row<float>(ln, j);
+        const float *src = red + (g * WC) * PER_WAVE + r;
+        float sum = src[0];
+#pragma unroll
+        for (int w = 1; w < WC; ++w) sum += src[w * PER_WAVE];
+        const int64_t row = (int64_t)blockIdx.x * 16 * MB * WM + 16 * MB * g + 16 * mb + acc_row<float>(ln, j);
         const int c = c0 + 16 * nb + (ln & 15);
         if (row < In && c < R) partial[((int64_t)blockIdx.y * In + row) * R + c] = sum;
     }
@@ -283,29 +298,36 @@ __global__ __launch_bounds__(kThreads) void k_contract_right_bf16(
     // X tile loader: thread -> (plane, 8-wide j group, row pair)
     const int plane = wave >> 1, tt = tid & 127, jg = tt & 7, rp = tt >> 3;  // rp in [0, 16)
     const bool jok = V8 ? (jt0 + 8 * jg < J) : true;
+    const bool jragged = jt0 + JT > J;
+    // Descriptor over the chunk's rows of the current outer block: rows past
+    // the chunk end lie outside its record count, and everything does once
+    // the split's blocks are exhausted.
+    const int64_t rows_valid = rend - r0;
+    const uint32_t rec = rows_valid == LC ? kRsrcRange : (uint32_t)(rows_valid * J * 2);
     int64_t lo = o_begin;
     int ls = 0;
-    rsrc_t rx = make_rsrc(Xp + (int64_t)plane * I + (o_begin < o_end ? o_begin : 0) * IR_in * J + r0 * J + jt0,
-                          kRsrcRange);
-    auto load_step = [&](f32x4 (&a)[2]) {
+    rsrc_t rx;
+    auto set_block = [&]() {
         const bool live = lo < o_end;
+        rx = make_rsrc(Xp + (live ? (int64_t)plane * I + lo * IR_in * J + r0 * J + jt0 : 0), live ? rec : 0u);
+    };
+    set_block();
+    auto load_step = [&](f32x4 (&a)[2]) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t rl = (int64_t)RS * ls + 2 * rp + h;  // row within the chunk
-            const bool ok = live && r0 + rl < rend;
+            uint32_t off = (uint32_t)((rl * J + 8 * jg) * 2);
             if (V8) {
-                const uint32_t off = (ok && jok) ? (uint32_t)((rl * J + 8 * jg) * 2) : kNoLoad;
+                if (jragged) off = jok ? off : kNoLoad;
                 a[h] = buf_load_raw16(rx, off);
             } else {
-                const uint32_t off = ok ? (uint32_t)((rl * J + 8 * jg) * 2) : kNoLoad;
                 a[h] = buf_load_raw16_scalar(rx, off, jt0 + 8 * jg, J);
             }
         }
         if (++ls == SPB) {
             ls = 0;
             ++lo;
-            if (lo < o_end)
-                rx = make_rsrc(Xp + (int64_t)plane * I + lo * IR_in * J + r0 * J + jt0, kRsrcRange);
+            set_block();
         }
     };
     // Transposed write: the two rows of this thread are adjacent in r, so each
@@ -335,15 +357,10 @@ __global__ __launch_bounds__(kThreads) void k_contract_right_bf16(
         kth[c * LCP + q] = hb;
         ktl[c * LCP + q] = bf16_rne_bits(v - bf16_bits_to_float(hb));
     });
-    const int cbase = c0 + 16 * wn * NBW + m;
-    int64_t co = o_begin;
+    float *stab = reinterpret_cast<float *>(xt + 2 * 2 * JT * XP);  // [scale_blocks<RP>()][RP] outer scales
+    if (has_out) fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
+    int64_t co = o_begin, tb0 = o_begin;
     int cs = 0;
-    KrpRowVals<float, NBW> sv;
-    KrpCursor<float> scur;
-    if (has_out && o_begin < o_end) {
-        scur.set(kout, o_begin);
-        sv.fetch(kout, R, cbase, scur);
-    }
 
     auto compute_step = [&](int buf) {
         const uint16_t *xb = xt + buf * 2 * JT * XP;
@@ -368,42 +385,46 @@ __global__ __launch_bounds__(kThreads) void k_contract_right_bf16(
             if (has_out) {
 #pragma unroll
                 for (int b = 0; b < NBW; ++b) {
-                    const float sval = sv.value(kout, R, cbase, b);
+                    const float sval = stab[(co - tb0) * RP + 16 * (wn * NBW + b) + m];
 #pragma unroll
                     for (int a = 0; a < MBW; ++a) {
                         tot[a][b] += acc[a][b] * sval;
                         acc[a][b] = f32x4{0, 0, 0, 0};
                     }
                 }
-                if (co + 1 < o_end) {
-                    scur.next(kout);
-                    sv.fetch(kout, R, cbase, scur);
-                }
             }
             ++co;
         }
     };
 
-    const int64_t nsteps = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
-    if (nsteps > 0) write_tile(x[0], 0);
-    __syncthreads();
-    // step st is computed from LDS buffer st & 1; its registers were x[st % DX]
-    int64_t st = 0;
-    for (; st + DX <= nsteps; st += DX) {
+    // Global step g is computed from LDS buffer g & 1; its registers were
+    // x[g % DX].  Chunks of scale_blocks<RP>() blocks (an even multiple of DX
+    // steps) keep both alignments; the scale table is refilled between
+    // chunks, behind the per-step barrier.
+    const int64_t total = (o_end > o_begin ? o_end - o_begin : 0) * SPB;
+    if (total > 0) write_tile(x[0], 0);
+    for (int64_t g0 = 0; g0 < total; g0 += (int64_t)scale_blocks<RP>() * SPB) {
+        tb0 = o_begin + g0 / SPB;
+        if (g0 != 0 && has_out) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
+        __syncthreads();
+        const int64_t gend = min(total, g0 + (int64_t)scale_blocks<RP>() * SPB);
+        int64_t g = g0;
+        for (; g + DX <= gend; g += DX) {
+#pragma unroll
+            for (int k = 0; k < DX; ++k) {
+                compute_step((int)((g + k) & 1));
+                if (g + k + 1 < total) write_tile(x[(k + 1) % DX], (int)((g + k + 1) & 1));
+                load_step(x[k]);  // step g + k + DX
+                __syncthreads();
+            }
+        }
 #pragma unroll
         for (int k = 0; k < DX; ++k) {
-            compute_step((int)((st + k) & 1));
-            if (st + k + 1 < nsteps) write_tile(x[(k + 1) % DX], (int)((st + k + 1) & 1));
-            load_step(x[k]);  // step st + k + DX
-            __syncthreads();
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < DX; ++k) {
-        if (st + k < nsteps) {
-            compute_step((int)((st + k) & 1));
-            if (st + k + 1 < nsteps) write_tile(x[(k + 1) % DX], (int)((st + k + 1) & 1));
-            __syncthreads();
+            if (g + k < gend) {
+                compute_step((int)((g + k) & 1));
+                if (g + k + 1 < total) write_tile(x[(k + 1) % DX], (int)((g + k + 1) & 1));
+                __syncthreads();
+            }
         }
     }
     if (!has_out) {

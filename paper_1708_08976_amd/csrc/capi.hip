@@ -89,6 +89,7 @@ struct Plan {
     int64_t n_outer;          // outer blocks
     int SPB, LC;              // steps per block per wave, inner chunk
     int Q;                    // left: 16-entry groups per row per step
+    int WMg = 1;              // split-bf16 left: wave groups on separate row tiles
     int64_t nlc, bps, S;      // inner chunks, blocks per split, splits
     int64_t ntiles;           // row tiles (left) / j tiles (right)
     bool v4;
@@ -123,6 +124,10 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
         p.kind = kBf16Left;
         p.MB = p.NB >= 4 ? 1 : 2;
         while (p.MB > 1 && 16 * p.MB / 2 >= p.In) p.MB /= 2;
+        // Wide ranks: waves take separate 16-row tiles and each streams the
+        // whole chunk, so a block spans several steps per wave and its
+        // scaling epilogue is amortised.
+        p.WMg = p.NB < 4 ? 1 : (p.In >= 64 ? 4 : (p.In >= 32 ? 2 : 1));
         const int64_t lcmax =
             std::max<int64_t>(128, std::min<int64_t>(512, (int64_t)(kTileBytes / (4 * RP) - 8) / 128 * 128));
         int q = 0;
@@ -133,12 +138,12 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
         p.G_out = p.IL / p.G_in;
         p.n_outer = p.G_out * p.IR;
         p.Q = (p.NB >= 8 || p.G_in <= 128) ? 1 : 2;
-        const int64_t unit = 128 * p.Q;
+        const int64_t unit = (4 / p.WMg) * 32 * p.Q;
         p.LC = (int)std::min<int64_t>(std::max<int64_t>(unit, lcmax / unit * unit), ceil_div(p.G_in, unit) * unit);
         p.SPB = p.LC / (int)unit;
         p.nlc = ceil_div(p.G_in, p.LC);
-        p.ntiles = ceil_div(p.In, 16 * p.MB);
-        const size_t tile = (size_t)4 * RP * (p.LC + 8);
+        p.ntiles = ceil_div(p.In, 16 * p.MB * p.WMg);
+        const size_t tile = (size_t)4 * RP * (p.LC + 8) + (size_t)kScaleTableBytes;
         const size_t red = (size_t)4 * p.MB * p.NB * 256 * 4;
         p.lds = std::max(tile, red);
         p.v4 = (p.G_in % 8 == 0) && (I % 8 == 0) && ((uintptr_t)X % 16 == 0);
@@ -159,7 +164,7 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
         p.SPB = p.LC / 32;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.J, 64);
-        p.lds = (size_t)4 * RP * (p.LC + 8) + kBf16XtBytes;
+        p.lds = (size_t)4 * RP * (p.LC + 8) + kBf16XtBytes + (size_t)kScaleTableBytes;
         p.v4 = (p.J % 8 == 0) && (I % 8 == 0) && ((uintptr_t)X % 16 == 0);
         p.max_offset = ((int64_t)p.LC * p.J + 64 + 8) * 2;
     }
@@ -205,7 +210,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.SPB = p.LC / (int)unit;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.In, 32 * p.MB);
-        p.lds = std::max((size_t)4 * RP * (p.LC + 4) + 16384 + (size_t)4 * kScaleBlocks * RP, (size_t)16384 * p.NB);
+        p.lds = std::max((size_t)4 * RP * (p.LC + 4) + 16384 + (size_t)kScaleTableBytes, (size_t)16384 * p.NB);
         p.v4 = true;
         p.max_offset = (31 * p.IL + p.LC + 4) * 4;
         p.J = p.In;
@@ -233,7 +238,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.SPB = p.LC / (int)unit;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.J, 32 * tj * wj);
-        p.lds = std::max((size_t)4 * RP * (p.LC + 4) + (size_t)4 * kScaleBlocks * RP,
+        p.lds = std::max((size_t)4 * RP * (p.LC + 4) + (size_t)kScaleTableBytes,
                          wj < 4 ? (size_t)16384 * tj * p.NB : (size_t)0);
         p.v4 = tj > 1;
         p.max_offset = ((int64_t)p.LC * p.J + 32 * tj + 4) * 4;
@@ -525,16 +530,16 @@ cpm_status run_mttkrp_t(const Plan &p, const void *Xv, const int64_t *dims, int 
     return CPM_OK;
 }
 
-template <int NB, int MB, int Q>
+template <int NB, int MB, int Q, int WM = 1>
 void launch_left_bf16_t(const Plan &p, const uint16_t *X, int64_t I, const Krp<float> &kin, const Krp<float> &kout,
                         int R, float *partial, hipStream_t st) {
     dim3 grid((unsigned)p.ntiles, (unsigned)(p.S * p.nlc), (unsigned)p.ncb);
     if (p.v4)
-        hipLaunchKernelGGL((k_contract_left_bf16<NB, MB, Q, true>), grid, dim3(kThreads), p.lds, st, X, I, p.G_in,
-                           p.G_out, p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+        hipLaunchKernelGGL((k_contract_left_bf16<NB, MB, Q, true, WM>), grid, dim3(kThreads), p.lds, st, X, I,
+                           p.G_in, p.G_out, p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
     else
-        hipLaunchKernelGGL((k_contract_left_bf16<NB, MB, Q, false>), grid, dim3(kThreads), p.lds, st, X, I, p.G_in,
-                           p.G_out, p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
+        hipLaunchKernelGGL((k_contract_left_bf16<NB, MB, Q, false, WM>), grid, dim3(kThreads), p.lds, st, X, I,
+                           p.G_in, p.G_out, p.In, p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
 }
 
 template <int NB, int MB>
@@ -586,8 +591,22 @@ cpm_status run_mttkrp_bf16(const Plan &p, const void *Xv, const int64_t *dims, i
         switch (p.NB) {
         case 1: launch_left_bf16_m<1>(p, X, I, kin, kout, R, partial, st); break;
         case 2: launch_left_bf16_m<2>(p, X, I, kin, kout, R, partial, st); break;
-        case 4: launch_left_bf16_q<4, 1>(p, X, I, kin, kout, R, partial, st); break;
-        default: launch_left_bf16_t<8, 1, 1>(p, X, I, kin, kout, R, partial, st); break;
+        case 4:
+            if (p.WMg == 4) {
+                if (p.Q == 2) launch_left_bf16_t<4, 1, 2, 4>(p, X, I, kin, kout, R, partial, st);
+                else launch_left_bf16_t<4, 1, 1, 4>(p, X, I, kin, kout, R, partial, st);
+            } else if (p.WMg == 2) {
+                if (p.Q == 2) launch_left_bf16_t<4, 1, 2, 2>(p, X, I, kin, kout, R, partial, st);
+                else launch_left_bf16_t<4, 1, 1, 2>(p, X, I, kin, kout, R, partial, st);
+            } else {
+                launch_left_bf16_q<4, 1>(p, X, I, kin, kout, R, partial, st);
+            }
+            break;
+        default:
+            if (p.WMg == 4) launch_left_bf16_t<8, 1, 1, 4>(p, X, I, kin, kout, R, partial, st);
+            else if (p.WMg == 2) launch_left_bf16_t<8, 1, 1, 2>(p, X, I, kin, kout, R, partial, st);
+            else launch_left_bf16_t<8, 1, 1>(p, X, I, kin, kout, R, partial, st);
+            break;
         }
         LAUNCH_CHECK("k_contract_left_bf16");
     } else {

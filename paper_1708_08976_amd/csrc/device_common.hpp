@@ -377,6 +377,31 @@ struct KrpRowVals {
     }
 };
 
+// Outer scales S(o, c) of up to scale_blocks<RP>() consecutive blocks, for
+// the work-group's RP rank columns, held in LDS ([block][RP], 6 KB).  The
+// stream runs in chunks of that many blocks; the table is refilled between
+// chunks (a barrier and one round of factor loads), outside the unrolled
+// step loop.  Reading a scale in the stream is an LDS access, so it never
+// waits on the in-order completion counter of the X loads in flight.  The
+// chunk length is a multiple of the register rings of the streaming kernels
+// (3 and 6), so every chunk starts on ring slot 0.
+constexpr int kScaleTableBytes = 6144;
+template <int RP>
+__host__ __device__ constexpr int scale_blocks() {
+    return kScaleTableBytes / 4 / RP;
+}
+static_assert(scale_blocks<128>() % 6 == 0 && scale_blocks<16>() % 6 == 0, "chunk must align with the rings");
+template <int RP>
+__device__ inline void fill_scales(const Krp<float> &kout, int R, int c0, int64_t ob, int64_t o_end, float *stab) {
+    constexpr int NBLK = scale_blocks<RP>();
+    if (kout.Z == 0) {
+        for (int e = threadIdx.x; e < NBLK * RP; e += kThreads) stab[e] = 1.f;
+        return;
+    }
+    build_tile_batched<float, RP, (NBLK * RP >= 8 * kThreads ? 8 : 4)>(
+        kout, R, c0, ob, NBLK, o_end, [&](int q, int c, float v) { stab[q * RP + c] = v; });
+}
+
 // ---------------------------------------------------------------------------
 // MFMA wrappers.  16x16x4 (f32, f64): lane l holds A[l%16][l/16] and
 // B[l/16][l%16].  Accumulator element j (0..3) of lane l holds

@@ -46,24 +46,6 @@ namespace cpm {
 //   grid.x = row tile (32*WM rows), grid.y = lc + nlc*split, grid.z = column
 //   block.  partial: [gridDim.y][In][R].
 // ---------------------------------------------------------------------------
-// Outer scales S(o, c) of up to kScaleBlocks consecutive blocks, for the
-// work-group's rank columns, held in LDS ([block][RP]).  The stream runs in
-// chunks of kScaleBlocks blocks; the table is refilled between chunks (a
-// barrier and one round of factor loads), outside the unrolled step loop.
-// Reading a scale in the stream is an LDS access, so it never waits on the
-// in-order completion counter of the X loads in flight.  kScaleBlocks is a
-// multiple of the register ring (3), so every chunk starts on ring slot 0.
-constexpr int kScaleBlocks = 48;
-template <int RP>
-__device__ inline void fill_scales(const Krp<float> &kout, int R, int c0, int64_t ob, int64_t o_end, float *stab) {
-    if (kout.Z == 0) {
-        for (int e = threadIdx.x; e < kScaleBlocks * RP; e += kThreads) stab[e] = 1.f;
-        return;
-    }
-    build_tile_batched<float, RP, 8>(kout, R, c0, ob, kScaleBlocks, o_end,
-                                     [&](int q, int c, float v) { stab[q * RP + c] = v; });
-}
-
 template <int NC, int WM, int RING = 3>
 __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X, int64_t IL_in, int64_t IL_out,
                                                      int64_t In, int64_t n_outer, Krp<float> kin,
@@ -136,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
     for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
     build_tile_batched<float, RP, 16>(kin, R, c0, l0, LC, IL_in, [&](int q, int c, float v) { tile[c * PT + q] = v; });
 
-    float *stab = stg + (4 - wave) * 32 * WS;  // [kScaleBlocks][RP], after the four staging slots
+    float *stab = stg + (4 - wave) * 32 * WS;  // [scale_blocks<RP>()][RP], after the four staging slots
     fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
     int64_t co = o_begin, tb0 = o_begin;
     int cs = 0;
@@ -172,18 +154,18 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
                 for (int nc = 0; nc < NC; ++nc) acc[nc] = mfma32(a[q][t], b[nc][q][t], acc[nc]);
         if (++cs == SPB) {
             cs = 0;
-            if (++co - tb0 < kScaleBlocks && co < o_end) load_scales();
+            if (++co - tb0 < scale_blocks<RP>() && co < o_end) load_scales();
         }
     };
 
-    // Chunks of kScaleBlocks blocks; within a chunk RING steps per pass with
+    // Chunks of scale_blocks<RP>() blocks; within a chunk RING steps per pass with
     // compile-time ring slots.
-    for (; tb0 < o_end; tb0 += kScaleBlocks) {
+    for (; tb0 < o_end; tb0 += scale_blocks<RP>()) {
         if (tb0 != o_begin) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
         __syncthreads();
         co = tb0;
         load_scales();
-        const int64_t nsteps = (min(o_end, tb0 + kScaleBlocks) - tb0) * SPB;
+        const int64_t nsteps = (min(o_end, tb0 + scale_blocks<RP>()) - tb0) * SPB;
         int64_t st = 0;
         for (; st + RING <= nsteps; st += RING) {
 #pragma unroll
@@ -318,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
     for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
     build_tile_batched<float, RP, 16>(kin, R, c0, r0, LC, IR_in, [&](int q, int c, float v) { tile[c * PT + q] = v; });
 
-    float *stab = tile + RP * PT;  // [kScaleBlocks][RP]
+    float *stab = tile + RP * PT;  // [scale_blocks<RP>()][RP]
     fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
     int64_t co = o_begin, tb0 = o_begin;
     int cs = 0;
@@ -347,16 +329,16 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
                 for (int nc = 0; nc < NC; ++nc) acc[t][nc] = mfma32(jcomp<TJ>(a[s], t), b[nc][s], acc[t][nc]);
         if (++cs == SPB) {
             cs = 0;
-            if (++co - tb0 < kScaleBlocks && co < o_end) load_scales();
+            if (++co - tb0 < scale_blocks<RP>() && co < o_end) load_scales();
         }
     };
 
-    for (; tb0 < o_end; tb0 += kScaleBlocks) {
+    for (; tb0 < o_end; tb0 += scale_blocks<RP>()) {
         if (tb0 != o_begin) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
         __syncthreads();
         co = tb0;
         load_scales();
-        const int64_t nsteps = (min(o_end, tb0 + kScaleBlocks) - tb0) * SPB;
+        const int64_t nsteps = (min(o_end, tb0 + scale_blocks<RP>()) - tb0) * SPB;
         int64_t st = 0;
         for (; st + RING <= nsteps; st += RING) {
 #pragma unroll
