@@ -124,20 +124,31 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
         p.kind = kBf16Left;
         p.MB = p.NB >= 4 ? 1 : 2;
         while (p.MB > 1 && 16 * p.MB / 2 >= p.In) p.MB /= 2;
-        // Wide ranks: waves take separate 16-row tiles and each streams the
-        // whole chunk, so a block spans several steps per wave and its
-        // scaling epilogue is amortised.
-        p.WMg = p.NB < 4 ? 1 : (p.In >= 64 ? 4 : (p.In >= 32 ? 2 : 1));
         const int64_t lcmax =
             std::max<int64_t>(128, std::min<int64_t>(512, (int64_t)(kTileBytes / (4 * RP) - 8) / 128 * 128));
+        // Inner range: the fastest left modes that fit one chunk (a single
+        // longer mode is cut into chunks).
         int q = 0;
         p.G_in = 1;
         while (q < mode && p.G_in * dims[q] <= lcmax) p.G_in *= dims[q++];
         if (q == 0) p.G_in = dims[q++];  // one long mode, cut into chunks
+        // Rows far apart (8 MB or more): take a longer inner range in chunks,
+        // so each row contributes a longer contiguous run per block (fewer
+        // pages touched per byte streamed).
+        if (p.IL * 2 >= ((int64_t)8 << 20))
+            while (q < mode && p.G_in < lcmax) p.G_in *= dims[q++];
         p.p = q;
         p.G_out = p.IL / p.G_in;
         p.n_outer = p.G_out * p.IR;
-        p.Q = (p.NB >= 8 || p.G_in <= 128) ? 1 : 2;
+        // Waves split the chunk (WC ways) and take separate 16*MB-row tiles
+        // (WM = 4 / WC ways).  Wide ranks prefer row tiles, so a block spans
+        // several steps per wave and its scaling epilogue is amortised; a
+        // short inner range needs them, so no step runs past it.
+        const int wc_fit = (int)std::max<int64_t>(1, std::min<int64_t>(4, p.G_in / 32));
+        int wm = p.NB < 4 ? 1 : (p.In >= 64 ? 4 : (p.In >= 32 ? 2 : 1));
+        while (4 / wm > wc_fit) wm *= 2;
+        p.WMg = wm;
+        p.Q = (p.NB >= 8 || p.G_in < 256 || wm > 1) ? 1 : 2;
         const int64_t unit = (4 / p.WMg) * 32 * p.Q;
         p.LC = (int)std::min<int64_t>(std::max<int64_t>(unit, lcmax / unit * unit), ceil_div(p.G_in, unit) * unit);
         p.SPB = p.LC / (int)unit;
@@ -568,6 +579,19 @@ void launch_right_bf16_t(const Plan &p, const uint16_t *X, int64_t I, const Krp<
                            p.n_outer, kin, kout, R, p.SPB, p.nlc, p.bps, partial);
 }
 
+// Narrow ranks with row-tile wave groups (short inner ranges).
+template <int NB>
+void launch_left_bf16_wm(const Plan &p, const uint16_t *X, int64_t I, const Krp<float> &kin,
+                         const Krp<float> &kout, int R, float *partial, hipStream_t st) {
+    if (p.MB == 2) {
+        if (p.WMg == 4) launch_left_bf16_t<NB, 2, 1, 4>(p, X, I, kin, kout, R, partial, st);
+        else launch_left_bf16_t<NB, 2, 1, 2>(p, X, I, kin, kout, R, partial, st);
+    } else {
+        if (p.WMg == 4) launch_left_bf16_t<NB, 1, 1, 4>(p, X, I, kin, kout, R, partial, st);
+        else launch_left_bf16_t<NB, 1, 1, 2>(p, X, I, kin, kout, R, partial, st);
+    }
+}
+
 cpm_status run_mttkrp_bf16(const Plan &p, const void *Xv, const int64_t *dims, int N, const void *const *factors,
                            int R, int mode, void *outv, void *ws, hipStream_t st) {
     int in_modes[CPM_MAX_MODES], out_modes[CPM_MAX_MODES], left_modes[CPM_MAX_MODES];
@@ -589,8 +613,14 @@ cpm_status run_mttkrp_bf16(const Plan &p, const void *Xv, const int64_t *dims, i
     float *partial = p.reduce ? reinterpret_cast<float *>(ws) : out;
     if (p.kind == kBf16Left) {
         switch (p.NB) {
-        case 1: launch_left_bf16_m<1>(p, X, I, kin, kout, R, partial, st); break;
-        case 2: launch_left_bf16_m<2>(p, X, I, kin, kout, R, partial, st); break;
+        case 1:
+            if (p.WMg == 1) launch_left_bf16_m<1>(p, X, I, kin, kout, R, partial, st);
+            else launch_left_bf16_wm<1>(p, X, I, kin, kout, R, partial, st);
+            break;
+        case 2:
+            if (p.WMg == 1) launch_left_bf16_m<2>(p, X, I, kin, kout, R, partial, st);
+            else launch_left_bf16_wm<2>(p, X, I, kin, kout, R, partial, st);
+            break;
         case 4:
             if (p.WMg == 4) {
                 if (p.Q == 2) launch_left_bf16_t<4, 1, 2, 4>(p, X, I, kin, kout, R, partial, st);
