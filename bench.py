@@ -84,29 +84,37 @@ def algo_bytes(dims, R, mode, xbytes):
 
 
 def time_modes(torch, _abi, X, dims, U, outs, ws, dt, steps, warmup, stream):
-    """Per-mode average launch time (ms) and the whole-step time (ms)."""
+    """Whole-step time (ms): `steps` passes over all modes between two HIP
+    events.  Per-mode time (ms per call): each mode's call repeated `steps`
+    times back to back between two events, so the figure is the launches'
+    own duration (contraction plus split reduction) without event records
+    in between."""
     timer = Timer(torch, stream)
     N = len(dims)
 
-    def one_step(evs=None):
-        for n in range(N):
-            if evs is not None:
-                evs[n][0].append(timer.event())
-            _abi.mttkrp(X, dims, U, n, out=outs[n], dtype=dt, workspace=ws)
-            if evs is not None:
-                evs[n][1].append(timer.event())
+    def call(n):
+        _abi.mttkrp(X, dims, U, n, out=outs[n], dtype=dt, workspace=ws)
 
     for _ in range(warmup):
-        one_step()
+        for n in range(N):
+            call(n)
     torch.cuda.synchronize()
-    evs = [([], []) for _ in range(N)]
     t0 = timer.event()
     for _ in range(steps):
-        one_step(evs)
+        for n in range(N):
+            call(n)
     t1 = timer.event()
     torch.cuda.synchronize()
     step_ms = t0.elapsed_time(t1) / steps
-    per_mode = [sum(a.elapsed_time(b) for a, b in zip(*evs[n])) / steps for n in range(N)]
+    per_mode = []
+    for n in range(N):
+        call(n)
+        a = timer.event()
+        for _ in range(steps):
+            call(n)
+        b = timer.event()
+        torch.cuda.synchronize()
+        per_mode.append(a.elapsed_time(b) / steps)
     return step_ms, per_mode
 
 
