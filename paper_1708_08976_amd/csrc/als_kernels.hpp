@@ -20,18 +20,46 @@ __global__ void k_set_scalar(double *dst, double v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
 }
 
-// Partial Grams over row blocks: part[b][a][c] = sum_{i in block b} U[i][a] U[i][c].
+// Partial Gram matrices of row blocks: part[b] = U_b^T U_b (R x R, float64)
+// for rows [b*rows_per_block, (b+1)*rows_per_block).  The work-group stages
+// its rows in LDS as float64, kGramStage values at a time, and each thread
+// accumulates its (a, c) entries over the staged rows in row order; entries
+// are covered in passes of kThreads * kGramEPT.  Fixed order throughout.
+constexpr int kGramStage = 4096;
+constexpr int kGramEPT = 16;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(const T *__restrict__ U, int64_t I, int R,
                                                            int64_t rows_per_block, double *__restrict__ part) {
+    __shared__ double su[kGramStage];
+    const int SR = max(1, kGramStage / R);  // rows per stage
     const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t i1 = min(I, i0 + rows_per_block);
     double *dst = part + (int64_t)blockIdx.x * R * R;
-    for (int e = threadIdx.x; e < R * R; e += kThreads) {
-        const int a = e / R, c = e % R;
-        double s = 0.0;
-        for (int64_t i = i0; i < i1; ++i) s += (double)U[i * R + a] * (double)U[i * R + c];
-        dst[e] = s;
+    for (int e0 = 0; e0 < R * R; e0 += kThreads * kGramEPT) {
+        double acc[kGramEPT];
+#pragma unroll
+        for (int k = 0; k < kGramEPT; ++k) acc[k] = 0.0;
+        for (int64_t s0 = i0; s0 < i1; s0 += SR) {
+            const int nr = (int)min((int64_t)SR, i1 - s0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < nr * R; e += kThreads) su[e] = (double)U[s0 * R + e];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kGramEPT; ++k) {
+                const int e = e0 + threadIdx.x + k * kThreads;
+                if (e < R * R) {
+                    const int a = e / R, c = e % R;
+                    double sum = acc[k];
+                    for (int i = 0; i < nr; ++i) sum += su[i * R + a] * su[i * R + c];
+                    acc[k] = sum;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kGramEPT; ++k) {
+            const int e = e0 + threadIdx.x + k * kThreads;
+            if (e < R * R) dst[e] = acc[k];
+        }
     }
 }
 
@@ -56,85 +84,95 @@ __global__ __launch_bounds__(kThreads) void k_hadamard_except(const double *__re
     H[e] = v;
 }
 
-// Cholesky H = L L^T of an R x R float64 matrix held in LDS by one work-group
-// (right-looking: scale the pivot column, update the trailing block).
-// Writes L (row-major, zero above the diagonal) and its transpose Lt.  If a
-// pivot is not positive the factorisation stops and *status is set to 1
-// (it is never cleared here, so one failure in a sweep is remembered).
+// Cholesky H = L L^T of an R x R float64 matrix held in LDS by one work-group.
+// Right-looking on the unscaled trailing matrix: step j subtracts
+// A[i][j] A[k][j] / d_j from every (i, k) with k <= i in the trailing block
+// (threads tile it 16 x 16), one barrier per step.  The pivot d_j = A[j][j]
+// never changes after step j, so L is formed at the end as
+// L[i][j] = A[i][j] / sqrt(d_j) (and L[j][j] = sqrt(d_j)).  Writes L
+// (row-major, zero above the diagonal) and its transpose Lt.  If a pivot is
+// not positive the factorisation stops and *status is set to 1 (it is never
+// cleared here, so one failure in a sweep is remembered).
 __global__ __launch_bounds__(kThreads) void k_cholesky(const double *__restrict__ H, int R,
                                                        double *__restrict__ L, double *__restrict__ Lt,
                                                        int *__restrict__ status) {
     extern __shared__ double A[];  // R x R
-    __shared__ int bad;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, ti = t >> 4, tk = t & 15;
     for (int e = t; e < R * R; e += kThreads) A[e] = H[e];
-    if (t == 0) bad = 0;
     __syncthreads();
     for (int j = 0; j < R; ++j) {
         const double d = A[j * R + j];
-        if (!(d > 0.0)) {
-            if (t == 0) bad = 1;
-            break;  // d is the same value in every thread: uniform exit
+        if (!(d > 0.0)) {  // d is the same value in every thread: uniform exit
+            if (t == 0) *status = 1;
+            return;
         }
-        const double ljj = sqrt(d);
-        __syncthreads();
-        for (int i = j + 1 + t; i < R; i += kThreads) A[i * R + j] /= ljj;
-        if (t == 0) A[j * R + j] = ljj;
-        __syncthreads();
-        const int w = R - j - 1;  // trailing block size
-        for (int e = t; e < w * w; e += kThreads) {
-            const int i = j + 1 + e / w, k = j + 1 + e % w;
-            if (k <= i) A[i * R + k] -= A[i * R + j] * A[k * R + j];
+        const double inv = 1.0 / d;
+        for (int i = j + 1 + ti; i < R; i += 16) {
+            const double aij = A[i * R + j] * inv;
+            for (int k = j + 1 + tk; k <= i; k += 16) A[i * R + k] -= aij * A[k * R + j];
         }
         __syncthreads();
-    }
-    __syncthreads();
-    if (bad) {
-        if (t == 0) *status = 1;
-        return;
     }
     for (int e = t; e < R * R; e += kThreads) {
         const int i = e / R, k = e % R;
-        const double v = (k <= i) ? A[e] : 0.0;
+        double v = 0.0;
+        if (k == i) v = sqrt(A[e]);
+        else if (k < i) v = A[e] / sqrt(A[k * R + k]);
         L[e] = v;
         Lt[k * R + i] = v;
     }
 }
 
 // Row-parallel solve x H = m for every row of M (H = L L^T): L y = m^T then
-// L^T x^T = y.  One wave per row; lane k holds entries k and k + 64 (R <= 128).
-// Skipped entirely when *status is set, leaving out untouched.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_chol_solve_rows(const double *__restrict__ L,
-                                                              const double *__restrict__ Lt,
+// L^T x^T = y.  One wave per row, rows_per_wave rows in turn; lane k holds
+// entries k and k + 64 (R <= 128).  With LDS_L the work-group first copies L
+// and L^T into LDS (2 R^2 doubles), so the 2R dependent steps of a row read
+// LDS instead of memory.  Skipped entirely when *status is set, leaving out
+// untouched.
+template <typename T, bool LDS_L>
+__global__ __launch_bounds__(kThreads) void k_chol_solve_rows(const double *__restrict__ Lg,
+                                                              const double *__restrict__ Ltg,
                                                               const int *__restrict__ status,
                                                               const T *__restrict__ M, int64_t In, int R,
-                                                              T *__restrict__ out) {
+                                                              int rows_per_wave, T *__restrict__ out) {
     if (*status) return;
+    extern __shared__ double sl[];
+    const double *L = Lg, *Lt = Ltg;
+    if (LDS_L) {
+        for (int e = threadIdx.x; e < R * R; e += kThreads) {
+            sl[e] = Lg[e];
+            sl[R * R + e] = Ltg[e];
+        }
+        __syncthreads();
+        L = sl;
+        Lt = sl + R * R;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t row = (int64_t)blockIdx.x * 4 + wave;
-    if (row >= In) return;
     const int k0 = lane, k1 = lane + 64;
-    double v0 = (k0 < R) ? (double)M[row * R + k0] : 0.0;
-    double v1 = (k1 < R) ? (double)M[row * R + k1] : 0.0;
-    for (int j = 0; j < R; ++j) {  // forward: column j of L is row j of Lt
-        const double src = (j < 64) ? v0 : v1;
-        const double yj = __shfl(src, j & 63) / L[j * R + j];
-        if (j < 64) { if (lane == j) v0 = yj; } else { if (lane == j - 64) v1 = yj; }
-        const double *col = Lt + (int64_t)j * R;
-        if (k0 > j && k0 < R) v0 -= col[k0] * yj;
-        if (k1 > j && k1 < R) v1 -= col[k1] * yj;
+    for (int rr = 0; rr < rows_per_wave; ++rr) {
+        const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * rows_per_wave + rr;
+        if (row >= In) break;
+        double v0 = (k0 < R) ? (double)M[row * R + k0] : 0.0;
+        double v1 = (k1 < R) ? (double)M[row * R + k1] : 0.0;
+        for (int j = 0; j < R; ++j) {  // forward: column j of L is row j of Lt
+            const double src = (j < 64) ? v0 : v1;
+            const double yj = __shfl(src, j & 63) / L[j * R + j];
+            if (j < 64) { if (lane == j) v0 = yj; } else { if (lane == j - 64) v1 = yj; }
+            const double *col = Lt + (int64_t)j * R;
+            if (k0 > j && k0 < R) v0 -= col[k0] * yj;
+            if (k1 > j && k1 < R) v1 -= col[k1] * yj;
+        }
+        for (int j = R - 1; j >= 0; --j) {  // backward: column j of L^T is row j of L
+            const double src = (j < 64) ? v0 : v1;
+            const double xj = __shfl(src, j & 63) / L[j * R + j];
+            if (j < 64) { if (lane == j) v0 = xj; } else { if (lane == j - 64) v1 = xj; }
+            const double *rowL = L + (int64_t)j * R;
+            if (k0 < j) v0 -= rowL[k0] * xj;
+            if (k1 < j && k1 < R) v1 -= rowL[k1] * xj;
+        }
+        if (k0 < R) out[row * R + k0] = (T)v0;
+        if (k1 < R) out[row * R + k1] = (T)v1;
     }
-    for (int j = R - 1; j >= 0; --j) {  // backward: column j of L^T is row j of L
-        const double src = (j < 64) ? v0 : v1;
-        const double xj = __shfl(src, j & 63) / L[j * R + j];
-        if (j < 64) { if (lane == j) v0 = xj; } else { if (lane == j - 64) v1 = xj; }
-        const double *rowL = L + (int64_t)j * R;
-        if (k0 < j) v0 -= rowL[k0] * xj;
-        if (k1 < j && k1 < R) v1 -= rowL[k1] * xj;
-    }
-    if (k0 < R) out[row * R + k0] = (T)v0;
-    if (k1 < R) out[row * R + k1] = (T)v1;
 }
 
 // Restore every factor from its snapshot when *status is set.
@@ -173,15 +211,18 @@ __device__ inline double block_sum(double v, double *sh) {
     return sh[0];
 }
 
-// *out = sum_e a[e] * b[e] in float64 (one work-group).
+// part[block] = sum over the block's grid-stride share of a[e] * b[e], in
+// float64 (a fixed split; k_sum_vector then adds the parts in order).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_dot(const T *__restrict__ a, const T *__restrict__ b, int64_t n,
-                                                  double *__restrict__ out) {
+__global__ __launch_bounds__(kThreads) void k_dot_partial(const T *__restrict__ a, const T *__restrict__ b,
+                                                          int64_t n, double *__restrict__ part) {
     __shared__ double sh[kThreads];
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < n; e += kThreads) s += (double)a[e] * (double)b[e];
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride)
+        s += (double)a[e] * (double)b[e];
     s = block_sum(s, sh);
-    if (threadIdx.x == 0) *out = s;
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // f = 1/2 (||X||^2 - 2 <M_{N-1}, U_{N-1}> + sum_ab prod_k G_k[a][b]); with

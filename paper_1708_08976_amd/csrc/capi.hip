@@ -715,7 +715,10 @@ struct SolveWs {
     size_t need;
 };
 
-constexpr int64_t kGramRows = 256;
+// Gram partials: about 32 rows per work-group, at most kGramBlocks slices.
+constexpr int64_t kGramRows = 32;
+constexpr int64_t kGramBlocks = 64;
+int64_t gram_blocks(int64_t I) { return std::min(kGramBlocks, ceil_div(I, kGramRows)); }
 constexpr int kSumsqBlocks = 1024;
 
 SolveWs layout_solve(const int64_t *dims, int N, int R, cpm_dtype dt, char *base, bool snapshot) {
@@ -730,7 +733,7 @@ SolveWs layout_solve(const int64_t *dims, int N, int R, cpm_dtype dt, char *base
     for (int k = 0; k < N; ++k) {
         maxI = std::max(maxI, dims[k]);
         sumI += dims[k];
-        maxblocks = std::max(maxblocks, ceil_div(dims[k], kGramRows));
+        maxblocks = std::max(maxblocks, gram_blocks(dims[k]));
     }
     const size_t fz = dtype_f_bytes(dt);
     w.status = (int *)take(sizeof(int));
@@ -752,9 +755,9 @@ SolveWs layout_solve(const int64_t *dims, int N, int R, cpm_dtype dt, char *base
 
 template <typename T>
 cpm_status gram_t(const T *U, int64_t I, int R, double *gpart, double *G, hipStream_t st) {
-    const int64_t blocks = ceil_div(I, kGramRows);
-    hipLaunchKernelGGL((k_gram_partial<T>), dim3((unsigned)blocks), dim3(kThreads), 0, st, U, I, R, kGramRows,
-                       gpart);
+    const int64_t blocks = gram_blocks(I);
+    const int64_t rows = ceil_div(I, blocks);
+    hipLaunchKernelGGL((k_gram_partial<T>), dim3((unsigned)blocks), dim3(kThreads), 0, st, U, I, R, rows, gpart);
     LAUNCH_CHECK("k_gram_partial");
     hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)ceil_div((int64_t)R * R, kThreads)), dim3(kThreads), 0, st,
                        gpart, blocks, (int64_t)R * R, G);
@@ -788,13 +791,21 @@ cpm_status hadamard_except(const double *grams, int N, int R, int skip, double *
     return CPM_OK;
 }
 
-cpm_status dot_enqueue(const void *a, const void *b, int64_t n, cpm_dtype dt, double *out, hipStream_t st) {
+// *out = <a, b> in float64: fixed-split partials into part (kDotBlocks
+// doubles), summed in order.
+constexpr int kDotBlocks = 64;
+cpm_status dot_enqueue(const void *a, const void *b, int64_t n, cpm_dtype dt, double *part, double *out,
+                       hipStream_t st) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, ceil_div(n, kThreads)));
     if (dt == CPM_F64)
-        hipLaunchKernelGGL(k_dot<double>, dim3(1), dim3(kThreads), 0, st, (const double *)a, (const double *)b, n,
-                           out);
+        hipLaunchKernelGGL(k_dot_partial<double>, dim3(blocks), dim3(kThreads), 0, st, (const double *)a,
+                           (const double *)b, n, part);
     else
-        hipLaunchKernelGGL(k_dot<float>, dim3(1), dim3(kThreads), 0, st, (const float *)a, (const float *)b, n, out);
-    LAUNCH_CHECK("k_dot");
+        hipLaunchKernelGGL(k_dot_partial<float>, dim3(blocks), dim3(kThreads), 0, st, (const float *)a,
+                           (const float *)b, n, part);
+    LAUNCH_CHECK("k_dot_partial");
+    hipLaunchKernelGGL(k_sum_vector, dim3(1), dim3(kThreads), 0, st, part, blocks, out);
+    LAUNCH_CHECK("k_sum_vector");
     return CPM_OK;
 }
 
@@ -908,13 +919,26 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
                                         (int)lds_chol));
         hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kThreads), lds_chol, stream, w.H, R, w.L, w.Lt, w.status);
         LAUNCH_CHECK("k_cholesky");
-        const unsigned blocks = (unsigned)ceil_div(dims[n], 4);
-        if (dt == CPM_F64)
-            hipLaunchKernelGGL(k_chol_solve_rows<double>, dim3(blocks), dim3(kThreads), 0, stream, w.L, w.Lt,
-                               w.status, (const double *)w.M, dims[n], R, (double *)factors[n]);
-        else
-            hipLaunchKernelGGL(k_chol_solve_rows<float>, dim3(blocks), dim3(kThreads), 0, stream, w.L, w.Lt,
-                               w.status, (const float *)w.M, dims[n], R, (float *)factors[n]);
+        // L and L^T go to LDS when they fit 64 KB (R <= 64); one row per wave.
+        const bool lds_l = R <= 64;
+        const int rpw = 1;
+        const unsigned blocks = (unsigned)ceil_div(dims[n], 4 * rpw);
+        const size_t lds_solve = lds_l ? (size_t)2 * R * R * sizeof(double) : 0;
+        if (dt == CPM_F64) {
+            if (lds_l)
+                hipLaunchKernelGGL((k_chol_solve_rows<double, true>), dim3(blocks), dim3(kThreads), lds_solve, stream,
+                                   w.L, w.Lt, w.status, (const double *)w.M, dims[n], R, rpw, (double *)factors[n]);
+            else
+                hipLaunchKernelGGL((k_chol_solve_rows<double, false>), dim3(blocks), dim3(kThreads), 0, stream, w.L,
+                                   w.Lt, w.status, (const double *)w.M, dims[n], R, rpw, (double *)factors[n]);
+        } else {
+            if (lds_l)
+                hipLaunchKernelGGL((k_chol_solve_rows<float, true>), dim3(blocks), dim3(kThreads), lds_solve, stream,
+                                   w.L, w.Lt, w.status, (const float *)w.M, dims[n], R, rpw, (float *)factors[n]);
+            else
+                hipLaunchKernelGGL((k_chol_solve_rows<float, false>), dim3(blocks), dim3(kThreads), 0, stream, w.L,
+                                   w.Lt, w.status, (const float *)w.M, dims[n], R, rpw, (float *)factors[n]);
+        }
         LAUNCH_CHECK("k_chol_solve_rows");
         s = gram(factors[n], dims[n], R, dt, w.gpart, w.grams + (size_t)n * R * R, stream);
         if (s) return s;
@@ -927,7 +951,7 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
             s = xnorm2_enqueue(X, total, dt, (double *)w.sumsq, w.xnorm2, stream);
             if (s) return s;
         }
-        s = dot_enqueue(w.M, factors[N - 1], dims[N - 1] * R, dt, w.inner, stream);
+        s = dot_enqueue(w.M, factors[N - 1], dims[N - 1] * R, dt, (double *)w.sumsq, w.inner, stream);
         if (s) return s;
         hipLaunchKernelGGL(k_loss, dim3(1), dim3(kThreads), 0, stream, w.xnorm2, w.inner, w.grams, N, R, 1,
                            w.result);
@@ -986,7 +1010,7 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
         s = run_mttkrp(p, X, dims, N, factors, R, n, w.M, dt, w.mws, stream);
         if (s) return s;
         if (want_inner) {
-            s = dot_enqueue(w.M, factors[n], dims[n] * R, dt, w.inner, stream);
+            s = dot_enqueue(w.M, factors[n], dims[n] * R, dt, (double *)w.sumsq, w.inner, stream);
             if (s) return s;
         }
         if (want_grad) {
