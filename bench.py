@@ -243,6 +243,16 @@ def extra_measurements(torch, _abi, inputs, X2, dims2, U2, stream):
     torch.cuda.synchronize()
     out["cp_als_sweep_512cube_r32"] = {"ms": round(t0.elapsed_time(t1) / reps, 3), "fit": round(fit, 6)}
 
+    # 20 CP-ALS sweeps from the N(0,1) start (seed 5), as in the 512^3 workload.
+    Ub = inputs.normal_factors(dims2, 32, seed=5, device="cuda")
+    torch.cuda.synchronize()
+    t0 = timer.event()
+    for _ in range(20):
+        fit = _abi.cp_als_step(X2, dims2, Ub, xnorm2=xn, want_fit=True, workspace=ws)
+    t1 = timer.event()
+    torch.cuda.synchronize()
+    out["cp_als_20_sweeps_512cube_r32"] = {"ms": round(t0.elapsed_time(t1), 3), "final_fit": round(fit, 6)}
+
     # 256x256x512x32 correlation-style tensor: float32 at R=64; split bf16
     # against float32 at R=128 (same tensor, same factors).
     dims3 = (256, 256, 512, 32)
