@@ -156,7 +156,9 @@ cpm_status cpm_split_bf16(const float *x, int64_t count, uint16_t *planes, hipSt
 /*
  * Rows [j0, j0 + nrows) of the Khatri-Rao product mats[0] kr ... kr
  * mats[Z-1] (Section 2.1: the last matrix's row index varies fastest),
- * formed by the same on-the-fly row builder the MTTKRP kernels use.
+ * formed on the device row by row, each row's multi-index stepped with
+ * carries and the slow partial Hadamard product reused across consecutive
+ * rows (Section 4.1).
  * mats: host array of Z device pointers to J_z x R row-major matrices
  * (float32 for CPM_F32, float64 for CPM_F64); out: device nrows x R.
  * 1 <= Z <= 12.

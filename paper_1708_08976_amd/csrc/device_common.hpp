@@ -227,92 +227,6 @@ __device__ inline void build_tile_batched(const Krp<T> &k, int R, int coff, int6
     }
 }
 
-// Two-phase tile form of the row builder for the MTTKRP kernels: rows
-// [row0, row0 + NROWS) of K, columns [coff, coff + RP).  Thread t owns
-// column t % RP and RUN = NROWS * RP / 256 consecutive rows.  fetch() issues
-// every global load of the thread's run into registers and returns without
-// waiting; put() multiplies and stores.  Kernels call fetch() for the next
-// tile, then issue their own loads and multiply the current tile, and call
-// put() afterwards, so the factor loads overlap the matrix work instead of
-// stalling it.  When RUN does not exceed the fastest factor's row count the
-// fastest index wraps at most once in a run: the run needs RUN rows of the
-// fastest factor and the slow partial Hadamard products (Algorithm 1's
-// stored products) at most at two multi-indices, whose first ZS factor
-// values are prefetched too.  Otherwise put() falls back to build_krp_rows.
-template <typename T, int RP, int NROWS>
-struct KrpTile {
-    static constexpr int RUN = NROWS * RP / kThreads;
-    static constexpr int ZS = 4;
-    static_assert(RUN >= 1 && RUN * kThreads == NROWS * RP, "tile must split evenly over the block");
-    T u[RUN];
-    T f0[ZS], f1[ZS];
-    int64_t g0, first_wrap;
-    bool fast;
-
-    __device__ inline void fetch(const Krp<T> &k, int R, int coff, int64_t row0, int64_t row_limit) {
-        const int t = threadIdx.x;
-        const int c = coff + t % RP;
-        const int64_t lim = min(row_limit, k.rows);
-        const bool col_ok = c < R;
-        g0 = row0 + (t / RP) * RUN;
-        fast = k.Z > 0 && k.J[0] >= RUN;
-        first_wrap = RUN;
-        if (!fast) return;
-        const int64_t J0 = k.J[0];
-        const int64_t i0 = mod64(g0, J0);
-        first_wrap = J0 - i0;
-        const T *__restrict__ U0 = k.U[0];
-#pragma unroll
-        for (int q = 0; q < RUN; ++q) {
-            int64_t idx = i0 + q;
-            if (idx >= J0) idx -= J0;
-            u[q] = (col_ok && g0 + q < lim) ? U0[idx * R + c] : T(0);
-        }
-        const int64_t g1 = g0 + first_wrap;
-        const bool ok0 = col_ok && g0 < lim;
-        const bool ok1 = col_ok && first_wrap < RUN && g1 < lim;
-#pragma unroll
-        for (int z = 0; z < ZS; ++z) {
-            const int zz = z + 1;
-            f0[z] = T(1);
-            f1[z] = T(1);
-            if (zz < k.Z) {
-                if (ok0) f0[z] = k.U[zz][mod64(div64(g0, k.stride[zz]), k.J[zz]) * R + c];
-                if (ok1) f1[z] = k.U[zz][mod64(div64(g1, k.stride[zz]), k.J[zz]) * R + c];
-            }
-        }
-    }
-
-    template <typename Store>
-    __device__ inline void put(const Krp<T> &k, int R, int coff, int64_t row0, int64_t row_limit, Store store) {
-        const int t = threadIdx.x;
-        const int cl = t % RP;
-        const int c = coff + cl;
-        const int q0 = (t / RP) * RUN;
-        const int64_t lim = min(row_limit, k.rows);
-        const bool col_ok = c < R;
-        if (k.Z == 0) {
-#pragma unroll
-            for (int q = 0; q < RUN; ++q) store(q0 + q, cl, (col_ok && row0 + q0 + q < lim) ? T(1) : T(0));
-            return;
-        }
-        if (!fast) {
-            build_krp_rows<T>(k, R, coff, RP, row0, NROWS, row_limit, store);
-            return;
-        }
-        T s0 = (f0[0] * f0[1]) * (f0[2] * f0[3]);
-        T s1 = (f1[0] * f1[1]) * (f1[2] * f1[3]);
-        const int64_t g1 = g0 + first_wrap;
-        for (int zz = ZS + 1; zz < k.Z; ++zz) {  // only for products of more than 5 factors
-            if (col_ok && g0 < lim) s0 *= k.U[zz][mod64(div64(g0, k.stride[zz]), k.J[zz]) * R + c];
-            if (col_ok && first_wrap < RUN && g1 < lim)
-                s1 *= k.U[zz][mod64(div64(g1, k.stride[zz]), k.J[zz]) * R + c];
-        }
-#pragma unroll
-        for (int q = 0; q < RUN; ++q) store(q0 + q, cl, (q < first_wrap ? s0 : s1) * u[q]);
-    }
-};
-
 // Multi-index of one row of a Khatri-Rao product, advanced one row at a time
 // with carries (no division after the first decode).  Digit z is the row of
 // factor z (fastest first).  Only the first kCursorZ factors are tracked

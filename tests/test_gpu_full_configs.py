@@ -156,3 +156,53 @@ def test_config5_64p5_fp32_sampled_rows_and_grad():
     ref_loss = 0.5 * O.residual2(Xh, dims, Uh)
     print("64^5 loss gpu %.10e oracle (direct) %.10e" % (loss.item(), ref_loss), flush=True)
     assert loss.item() == pytest.approx(ref_loss, rel=1e-6)
+
+
+def test_config3_sym4d_fp32_r128_sampled_rows():
+    """The float32 side of the split-bf16 comparison (four 32-column blocks
+    per work-group)."""
+    dims, R = (256, 256, 512, 32), 128
+    announce("256x256x512x32 fp32 R=128")
+    X = inputs.symmetric_pair_tensor(dims, seed=6, device="cuda")
+    U = inputs.normal_factors(dims, R, seed=8, device="cuda")
+    got = gpu_all_modes(X, dims, U)
+    check_sampled(got, X.cpu().numpy().ravel(), dims, [u.cpu().numpy() for u in U], TOL["f32"], "sym4d f32 R128")
+
+
+@pytest.mark.parametrize("R", [32, 128])
+def test_config5_64p5_split_bf16_sampled_rows_and_grad(R):
+    """The split-bf16 MTTKRPs and gradient that the benchmark times on 64^5
+    (the last mode's rows are 32 MB apart)."""
+    dims = (64,) * 5
+    announce("64^5 split bf16 R=%d" % R)
+    X, _ = inputs.noisy_low_rank(dims, 32, seed_factors=9, seed_noise=10, eta=0.05, device="cuda")
+    P = _abi.split_bf16(X.reshape(-1))
+    U = inputs.normal_factors(dims, R, seed=11, device="cuda")
+    Xh = X.cpu().numpy().ravel()
+    Uh = [u.cpu().numpy().astype(np.float64) for u in U]
+    got = gpu_all_modes(P, dims, U, dtype=_abi.CPM_BF16X2)
+    check_sampled(got, Xh, dims, Uh, TOL["bf16x2"], "64^5 bf16x2 R%d" % R)
+    if R == 32:
+        xn = O.xnorm2(Xh, dims)
+        grads, _ = _abi.cp_grad(P, dims, U, xnorm2=xn, dtype=_abi.CPM_BF16X2)
+        torch.cuda.synchronize()
+        for n in range(5):
+            rows = sample_rows(dims[n])
+            H = np.ones((R, R))
+            for k in range(5):
+                if k != n:
+                    H *= Uh[k].T @ Uh[k]
+            ref = Uh[n][rows] @ H - O.mttkrp_rows(Xh, dims, Uh, n, rows)
+            e = rel_err(grads[n].cpu().numpy()[rows], ref)
+            print("64^5 bf16x2 grad mode %d: relative error %.3e" % (n, e), flush=True)
+            assert e <= TOL["bf16x2"], (n, e)
+
+
+def test_config5_64p5_fp32_r128_sampled_rows():
+    dims, R = (64,) * 5, 128
+    announce("64^5 fp32 R=128")
+    X, _ = inputs.noisy_low_rank(dims, 32, seed_factors=9, seed_noise=10, eta=0.05, device="cuda")
+    U = inputs.normal_factors(dims, R, seed=11, device="cuda")
+    got = gpu_all_modes(X, dims, U)
+    check_sampled(got, X.cpu().numpy().ravel(), dims, [u.cpu().numpy().astype(np.float64) for u in U], TOL["f32"],
+                  "64^5 f32 R128")

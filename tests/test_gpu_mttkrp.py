@@ -155,3 +155,25 @@ def test_split_bf16_bit_exact_and_xnorm2():
     dims = (1000, 37)
     got = _abi.xnorm2(x.cuda(), dims).item()
     assert got == pytest.approx(O.xnorm2(x.numpy().ravel(), dims), rel=1e-13)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
+@pytest.mark.parametrize("R", [8, 40, 130])
+def test_many_blocks_per_work_group(dtype, R):
+    """A long outer range (40000 blocks for mode 1) gives every work-group
+    more blocks than one scale table holds, so the table is refilled
+    between chunks; every mode against the oracle."""
+    dims = (32, 8, 40000)
+    announce("many blocks", dtype, dims, R)
+    X, U = make_case(dims, R, seed=R + 5)
+    Ud = [u.cuda() for u in U]
+    if dtype == "f32":
+        Xd, code, xh, xt = X.cuda(), _abi.CPM_F32, X.numpy().ravel(), None
+    else:
+        planes = inputs.split_bf16_planes(X)
+        Xd, code, xh, xt = planes.cuda(), _abi.CPM_BF16X2, planes.numpy().view(np.uint16), O.BF16PAIR
+    absr = oracle_abs_all_modes(X, dims, U)
+    for n in range(3):
+        ref = O.mttkrp(xh, dims, [u.numpy() for u in U], n, xtype=xt)
+        got = _abi.mttkrp(Xd, dims, Ud, n, dtype=code).cpu().numpy()
+        assert rel_err_abs(got, ref, absr[n]) <= TOL[dtype], (n, R)
