@@ -246,24 +246,46 @@ __global__ __launch_bounds__(kThreads) void k_loss(const double *__restrict__ xn
 }
 
 // Per-block partial sums of squares of the tensor entries (bf16 pairs are
-// widened to hi + lo, which is exact in float32).
+// widened to hi + lo, which is exact in float32).  With vec (16-byte aligned
+// data, I a multiple of 8) the entries are read 16 bytes at a time: groups of
+// 4 floats, or 8 hi and 8 lo values.  A fixed split, summed in float64.
 template <int DT>
-__global__ __launch_bounds__(kThreads) void k_sumsq_partial(const void *__restrict__ Xv, int64_t I,
+__global__ __launch_bounds__(kThreads) void k_sumsq_partial(const void *__restrict__ Xv, int64_t I, int vec,
                                                             double *__restrict__ part) {
     __shared__ double sh[kThreads];
     double s = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < I; e += stride) {
-        double x;
-        if (DT == CPM_F32) {
-            x = (double)((const float *)Xv)[e];
-        } else if (DT == CPM_F64) {
-            x = ((const double *)Xv)[e];
-        } else {
-            const uint16_t *p = (const uint16_t *)Xv;
-            x = (double)(bf16_bits_to_float(p[e]) + bf16_bits_to_float(p[I + e]));
+    const int64_t t0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (vec && DT == CPM_F32) {
+        const f32x4 *x4 = (const f32x4 *)Xv;
+        for (int64_t g = t0; g < I / 4; g += stride) {
+            const f32x4 v = x4[g];
+            s += (double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2] + (double)v[3] * v[3];
         }
-        s += x * x;
+    } else if (vec && DT == CPM_BF16X2) {
+        const u16x8 *h8 = (const u16x8 *)Xv;
+        const u16x8 *l8 = (const u16x8 *)((const uint16_t *)Xv + I);
+        for (int64_t g = t0; g < I / 8; g += stride) {
+            const u16x8 h = h8[g], l = l8[g];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const double x = (double)(bf16_bits_to_float(h[e]) + bf16_bits_to_float(l[e]));
+                s += x * x;
+            }
+        }
+    } else {
+        for (int64_t e = t0; e < I; e += stride) {
+            double x;
+            if (DT == CPM_F32) {
+                x = (double)((const float *)Xv)[e];
+            } else if (DT == CPM_F64) {
+                x = ((const double *)Xv)[e];
+            } else {
+                const uint16_t *p = (const uint16_t *)Xv;
+                x = (double)(bf16_bits_to_float(p[e]) + bf16_bits_to_float(p[I + e]));
+            }
+            s += x * x;
+        }
     }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -278,14 +300,52 @@ __global__ __launch_bounds__(kThreads) void k_sum_vector(const double *__restric
     if (threadIdx.x == 0) *out = s;
 }
 
-// hi = RNE(x), lo = RNE(x - hi): the bf16 pair format.
-__global__ __launch_bounds__(kThreads) void k_split_bf16(const float *__restrict__ x, int64_t n,
+// hi = RNE(x), lo = RNE(x - hi): the bf16 pair format.  With vec8 (x 16-byte
+// aligned and n a multiple of 8, so both planes are 16-byte aligned too) each
+// thread converts groups of 8 values: two 16-byte loads, one 16-byte store
+// per plane.
+__device__ inline void split_one(float v, uint16_t &h, uint16_t &l) {
+    h = bf16_rne_bits(v);
+    l = bf16_rne_bits(v - bf16_bits_to_float(h));
+}
+__global__ __launch_bounds__(kThreads) void k_split_bf16(const float *__restrict__ x, int64_t n, int vec8,
                                                          uint16_t *__restrict__ planes) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
-        const float v = x[e];
-        const uint16_t h = bf16_rne_bits(v);
-        const uint16_t l = bf16_rne_bits(v - bf16_bits_to_float(h));
+    const int64_t t0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (vec8) {
+        const f32x4 *x4 = reinterpret_cast<const f32x4 *>(x);
+        u16x8 *hi8 = reinterpret_cast<u16x8 *>(planes);
+        u16x8 *lo8 = reinterpret_cast<u16x8 *>(planes + n);
+        auto convert = [&](const f32x4 &a, const f32x4 &b, int64_t g) {
+            u16x8 h, l;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint16_t hh, ll;
+                split_one(a[e], hh, ll);
+                h[e] = hh;
+                l[e] = ll;
+                split_one(b[e], hh, ll);
+                h[4 + e] = hh;
+                l[4 + e] = ll;
+            }
+            hi8[g] = h;
+            lo8[g] = l;
+        };
+        const int64_t n8 = n / 8;
+        int64_t g = t0;
+        // two groups (four 16-byte loads) in flight per thread, then the tail
+        for (; g + stride < n8; g += 2 * stride) {
+            const f32x4 a0 = x4[2 * g], b0 = x4[2 * g + 1];
+            const f32x4 a1 = x4[2 * (g + stride)], b1 = x4[2 * (g + stride) + 1];
+            convert(a0, b0, g);
+            convert(a1, b1, g + stride);
+        }
+        for (; g < n8; g += stride) convert(x4[2 * g], x4[2 * g + 1], g);
+        return;
+    }
+    for (int64_t e = t0; e < n; e += stride) {
+        uint16_t h, l;
+        split_one(x[e], h, l);
         planes[e] = h;
         planes[n + e] = l;
     }

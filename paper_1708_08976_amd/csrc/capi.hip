@@ -772,12 +772,13 @@ cpm_status gram(const void *U, int64_t I, int R, cpm_dtype dt, double *gpart, do
 
 cpm_status xnorm2_enqueue(const void *X, int64_t total, cpm_dtype dt, double *part, double *out, hipStream_t st) {
     const int blocks = (int)std::min<int64_t>(kSumsqBlocks, ceil_div(total, kThreads));
+    const int vec = ((uintptr_t)X % 16 == 0 && total % 8 == 0) ? 1 : 0;
     if (dt == CPM_F32)
-        hipLaunchKernelGGL(k_sumsq_partial<CPM_F32>, dim3(blocks), dim3(kThreads), 0, st, X, total, part);
+        hipLaunchKernelGGL(k_sumsq_partial<CPM_F32>, dim3(blocks), dim3(kThreads), 0, st, X, total, vec, part);
     else if (dt == CPM_F64)
-        hipLaunchKernelGGL(k_sumsq_partial<CPM_F64>, dim3(blocks), dim3(kThreads), 0, st, X, total, part);
+        hipLaunchKernelGGL(k_sumsq_partial<CPM_F64>, dim3(blocks), dim3(kThreads), 0, st, X, total, 0, part);
     else
-        hipLaunchKernelGGL(k_sumsq_partial<CPM_BF16X2>, dim3(blocks), dim3(kThreads), 0, st, X, total, part);
+        hipLaunchKernelGGL(k_sumsq_partial<CPM_BF16X2>, dim3(blocks), dim3(kThreads), 0, st, X, total, vec, part);
     LAUNCH_CHECK("k_sumsq_partial");
     hipLaunchKernelGGL(k_sum_vector, dim3(1), dim3(kThreads), 0, st, part, blocks, out);
     LAUNCH_CHECK("k_sum_vector");
@@ -1068,7 +1069,8 @@ cpm_status cpm_split_bf16(const float *x, int64_t count, uint16_t *planes, hipSt
     if (count < 0) return fail(CPM_EINVAL, "count < 0");
     if (count == 0) return CPM_OK;
     const unsigned blocks = (unsigned)std::min<int64_t>(4096, ceil_div(count, kThreads));
-    hipLaunchKernelGGL(k_split_bf16, dim3(blocks), dim3(kThreads), 0, stream, x, count, planes);
+    const int vec8 = ((uintptr_t)x % 16 == 0 && (uintptr_t)planes % 16 == 0 && count % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_split_bf16, dim3(blocks), dim3(kThreads), 0, stream, x, count, vec8, planes);
     LAUNCH_CHECK("k_split_bf16");
     return CPM_OK;
 }

@@ -147,14 +147,32 @@ def test_krp_rows_matches_oracle(Js, R, dtype):
     np.testing.assert_allclose(part, ref[j0:-1], rtol=tol, atol=tol)
 
 
-def test_split_bf16_bit_exact_and_xnorm2():
-    x = inputs.normal_tensor((1000, 37), seed=9)
-    planes = _abi.split_bf16(x.cuda()).cpu()
+@pytest.mark.parametrize("dims,offset", [((1000, 37), 0), ((999, 37), 0), ((1000, 37), 1), ((64, 64, 64), 4)])
+def test_split_bf16_bit_exact_and_xnorm2(dims, offset):
+    """Both helpers on 16-byte-aligned data whose size is a multiple of 8
+    (vector loads) and on an odd size or a shifted start (scalar loads)."""
+    announce("split/xnorm2", dims, offset)
+    n = int(np.prod(dims))
+    x = inputs.normal_tensor(dims, seed=9).reshape(-1)
+    buf = torch.zeros(n + offset, device="cuda")
+    buf[offset:] = x.cuda()
+    xd = buf[offset:]
+    pbuf = torch.zeros(2 * n + 2 * offset, dtype=torch.int16, device="cuda")
+    planes_d = pbuf[2 * offset:]
+    _abi.split_bf16(xd, planes=planes_d)
     want = inputs.split_bf16_planes(x)
-    assert torch.equal(planes, want)
-    dims = (1000, 37)
-    got = _abi.xnorm2(x.cuda(), dims).item()
-    assert got == pytest.approx(O.xnorm2(x.numpy().ravel(), dims), rel=1e-13)
+    assert torch.equal(planes_d.cpu(), want)
+    xh = x.numpy()
+    # every square is exact in float64 (24- or 16-bit significands), so each
+    # side's sum of n non-negative terms is within (n - 1) 2^-53 relative of
+    # the exact value, whatever its order
+    tol = 2 * n * 2.0 ** -53
+    got = _abi.xnorm2(xd, dims).item()
+    assert got == pytest.approx(O.xnorm2(xh, dims), rel=tol)
+    # the pair tensor's squared norm: the oracle on the pair values
+    gotp = _abi.xnorm2(planes_d, dims, dtype=_abi.CPM_BF16X2).item()
+    refp = O.xnorm2(want.numpy().view(np.uint16), dims, xtype=O.BF16PAIR)
+    assert gotp == pytest.approx(refp, rel=tol)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
