@@ -313,10 +313,41 @@ def extra_measurements(torch, _abi, inputs, X2, dims2, U2, stream):
             torch.cuda.synchronize()
             ms = t0.elapsed_time(t1) / reps
             res[tag] = ms
+            # The five MTTKRPs: with the cross-mode reuse (two passes over X,
+            # modes split 2 | 3) and as five ordinary one-mode calls.
+            outs5 = [torch.empty_like(u) for u in U5]
+            wsa = torch.empty(max(1, _abi.mttkrp_all_workspace_bytes(dims5, R5, dt)), dtype=torch.uint8, device=dev)
+            wsm = torch.empty(max(1, max(_abi.mttkrp_workspace_bytes(dims5, R5, n, dt) for n in range(5))),
+                              dtype=torch.uint8, device=dev)
+
+            def all_modes():
+                _abi.mttkrp_all(Xin, dims5, U5, outs=outs5, dtype=dt, workspace=wsa)
+
+            def one_by_one():
+                for n in range(5):
+                    _abi.mttkrp(Xin, dims5, U5, n, out=outs5[n], dtype=dt, workspace=wsm)
+
+            t_mode = {}
+            for name, fn in (("reuse", all_modes), ("per_mode", one_by_one)):
+                fn()
+                a = timer.event()
+                for _ in range(reps):
+                    fn()
+                b = timer.event()
+                torch.cuda.synchronize()
+                t_mode[name] = a.elapsed_time(b) / reps
+            # algorithmic bytes: X twice, each group intermediate written
+            # once and read by every leaf of its group (s = 2 of 5 modes)
+            inter = (64 ** 2 * 3 + 64 ** 3 * 4) * R5 * 4
+            two_pass = 2 * 4 * 64 ** 5 + inter
             out["cp_grad_64p5_r%d_%s" % (R5, tag)] = {
                 "ms_per_eval": round(ms, 3), "evals_per_s": round(1e3 / ms, 2),
-                "hbm_roofline_evals_per_s": round(HBM_PEAK_GBS * 1e9 / (5 * 4 * 64 ** 5), 1)}
-            del ws5
+                "hbm_roofline_evals_per_s": round(HBM_PEAK_GBS * 1e9 / two_pass, 1),
+                "hbm_roofline_evals_per_s_one_pass_per_mode": round(HBM_PEAK_GBS * 1e9 / (5 * 4 * 64 ** 5), 1),
+                "five_mttkrps_ms_cross_mode_reuse": round(t_mode["reuse"], 3),
+                "five_mttkrps_ms_one_pass_per_mode": round(t_mode["per_mode"], 3),
+                "cross_mode_reuse_speedup": round(t_mode["per_mode"] / t_mode["reuse"], 3)}
+            del ws5, wsa, wsm, outs5
         out["cp_grad_64p5_r%d_split_bf16_speedup_over_fp32" % R5] = round(res["fp32"] / res["bf16x2"], 3)
         del U5, grads
     del X5, P5

@@ -103,6 +103,32 @@ cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *
                   int mode, void *out, cpm_dtype dt, void *workspace, size_t ws_bytes,
                   hipStream_t stream);
 
+/*
+ * Bytes of workspace `mttkrp_all` needs (0 for invalid arguments).
+ */
+size_t cpm_mttkrp_all_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);
+
+/*
+ * The MTTKRPs of several modes with the same factors (Section 2.2's
+ * definition for every requested mode), with the reuse of partial results
+ * across modes that the Conclusion names as the next step (after Phan et
+ * al.).  X, dims, factors, R, dt as for `mttkrp`, except that every factor
+ * is read.  outs: host array of N device pointers, outs[n] an I_n x R
+ * output or null to skip mode n.  From N = 4 on, when three or more modes
+ * are requested, the modes are split into a left group [0, s) and a right
+ * group [s, N): one pass over X contracts the right group and one the left,
+ * each leaving an intermediate of (entries of its group) x R values in the
+ * workspace, and every requested mode then follows from its group's
+ * intermediate -- two passes over X instead of one per mode.  The split is
+ * chosen so that the intermediates move fewer entries than one pass over X;
+ * otherwise (and for N < 4) each mode is an ordinary `mttkrp`.  The result
+ * agrees with `mttkrp` to rounding (a different summation order) and is
+ * bitwise reproducible run to run.  Stream-ordered, no synchronisation.
+ */
+cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                      void *const *outs, cpm_dtype dt, void *workspace, size_t ws_bytes,
+                      hipStream_t stream);
+
 /* Bytes of workspace for cp_als_step / cp_grad. */
 size_t cpm_cp_als_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);
 size_t cpm_cp_grad_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);
@@ -118,6 +144,10 @@ size_t cpm_cp_grad_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype 
  * fit_out: host pointer, may be null; receives 1 - ||X - Y|| / ||X|| of the
  * updated model (from ||X||^2 - 2 <M_{N-1}, U_{N-1}> + sum(Hadamard of all
  * Grams), accumulated in float64).  Waits for the stream once.
+ * From N = 4 on the MTTKRPs come from the two passes of `mttkrp_all`: the
+ * left group's intermediate depends only on factors not yet updated when
+ * it is formed, and the right group's is formed after the left group's
+ * updates, so the sweep is the same Gauss-Seidel order.
  * R <= 128.
  */
 cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *factors, int R,
@@ -132,6 +162,8 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
  * 1/2 (||X||^2 - 2 <MTTKRP_{N-1}, U_{N-1}> + sum(Hadamard of all Grams)),
  * accumulated in float64, the residual itself never being formed.
  * xnorm2: ||X||_F^2 if known, negative to compute it on the device.
+ * The MTTKRPs are formed as by `mttkrp_all` (two passes over X from N = 4
+ * on when three or more modes are wanted).
  * R <= 128.
  */
 cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const *factors, int R,

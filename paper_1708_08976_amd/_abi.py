@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_EUNSUPPORTED", 3: "CPM_ENO
                 4: "CPM_EHIP", 5: "CPM_EWORKSPACE"}
 
 EXPORTS = ["cpm_version", "cpm_last_error", "cpm_mttkrp_workspace_bytes", "mttkrp",
+           "cpm_mttkrp_all_workspace_bytes", "mttkrp_all",
            "cpm_cp_als_workspace_bytes", "cpm_cp_grad_workspace_bytes", "cp_als_step", "cp_grad",
            "cpm_xnorm2_workspace_bytes", "cpm_xnorm2", "cpm_split_bf16", "cpm_krp_rows"]
 
@@ -49,6 +50,10 @@ def load():
     lib.cpm_mttkrp_workspace_bytes.restype = sz
     lib.mttkrp.argtypes = [vp, i64p, ci, vpp, ci, ci, vp, ci, vp, sz, vp]
     lib.mttkrp.restype = ci
+    lib.cpm_mttkrp_all_workspace_bytes.argtypes = [i64p, ci, ci, ci]
+    lib.cpm_mttkrp_all_workspace_bytes.restype = sz
+    lib.mttkrp_all.argtypes = [vp, i64p, ci, vpp, ci, vpp, ci, vp, sz, vp]
+    lib.mttkrp_all.restype = ci
     lib.cpm_cp_als_workspace_bytes.argtypes = [i64p, ci, ci, ci]
     lib.cpm_cp_als_workspace_bytes.restype = sz
     lib.cpm_cp_grad_workspace_bytes.argtypes = [i64p, ci, ci, ci]
@@ -139,6 +144,37 @@ def mttkrp(X, dims, factors, mode, out=None, dtype=None, workspace=None, stream=
     _check(lib.mttkrp(X.data_ptr(), _dims(dims), len(dims), _ptrs(factors), R, int(mode), out.data_ptr(), dt,
                       ws_ptr, ws_len, _stream(X.device, stream)))
     return out
+
+
+def mttkrp_all_workspace_bytes(dims, R, dtype):
+    return load().cpm_mttkrp_all_workspace_bytes(_dims(dims), len(dims), int(R), int(dtype))
+
+
+def mttkrp_all(X, dims, factors, outs=None, modes=None, dtype=None, workspace=None, stream=None):
+    """MTTKRPs of every mode in `modes` (default: all) with the same factors
+    -> list of N outputs (None where a mode was not requested)."""
+    lib = load()
+    dt = _dtype_code(X, dtype)
+    _require(X, "X")
+    R = int(factors[0].shape[1])
+    for k, f in enumerate(factors):
+        _require(f, "factors[%d]" % k)
+    fdt = torch.float64 if dt == CPM_F64 else torch.float32
+    if outs is None:
+        want = set(range(len(dims))) if modes is None else set(modes)
+        outs = [torch.empty((int(d), R), dtype=fdt, device=X.device) if n in want else None
+                for n, d in enumerate(dims)]
+    for n, o in enumerate(outs):
+        if o is not None:
+            _require(o, "outs[%d]" % n)
+    need = lib.cpm_mttkrp_all_workspace_bytes(_dims(dims), len(dims), R, dt)
+    if workspace is None:
+        workspace = _workspace(need, X.device)
+    _check(lib.mttkrp_all(X.data_ptr(), _dims(dims), len(dims), _ptrs(factors), R, _ptrs(outs), dt,
+                          None if workspace is None else workspace.data_ptr(),
+                          0 if workspace is None else workspace.numel() * workspace.element_size(),
+                          _stream(X.device, stream)))
+    return outs
 
 
 def cp_als_workspace_bytes(dims, R, dtype):

@@ -21,46 +21,59 @@ __global__ void k_set_scalar(double *dst, double v) {
 }
 
 // Partial Gram matrices of row blocks: part[b] = U_b^T U_b (R x R, float64)
-// for rows [b*rows_per_block, (b+1)*rows_per_block).  The work-group stages
-// its rows in LDS as float64, kGramStage values at a time, and each thread
-// accumulates its (a, c) entries over the staged rows in row order; entries
-// are covered in passes of kThreads * kGramEPT.  Fixed order throughout.
+// for rows [b*rows_per_block, (b+1)*rows_per_block) (grid.x = b).  Each
+// thread owns a 4 x 4 tile of entries (grid.y takes groups of kThreads
+// tiles), so a staged row costs 8 LDS reads for 16 multiply-adds.  The
+// work-group stages its rows in LDS as float64 (row pitch R rounded up to 4,
+// zero padded), and every entry is summed over the rows in row order.
 constexpr int kGramStage = 4096;
-constexpr int kGramEPT = 16;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(const T *__restrict__ U, int64_t I, int R,
                                                            int64_t rows_per_block, double *__restrict__ part) {
-    __shared__ double su[kGramStage];
-    const int SR = max(1, kGramStage / R);  // rows per stage
+    __shared__ __attribute__((aligned(32))) double su[kGramStage];
+    const int RP = (R + 3) & ~3;
+    const int TR = RP / 4;                  // tiles per row of the Gram matrix
+    const int SR = max(1, kGramStage / RP); // rows per stage
     const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t i1 = min(I, i0 + rows_per_block);
-    double *dst = part + (int64_t)blockIdx.x * R * R;
-    for (int e0 = 0; e0 < R * R; e0 += kThreads * kGramEPT) {
-        double acc[kGramEPT];
+    const int t = (int)blockIdx.y * kThreads + threadIdx.x;
+    const bool own = t < TR * TR;
+    const int a0 = own ? 4 * (t / TR) : 0, c0 = own ? 4 * (t % TR) : 0;
+    double acc[4][4];
 #pragma unroll
-        for (int k = 0; k < kGramEPT; ++k) acc[k] = 0.0;
-        for (int64_t s0 = i0; s0 < i1; s0 += SR) {
-            const int nr = (int)min((int64_t)SR, i1 - s0);
-            __syncthreads();
-            for (int e = threadIdx.x; e < nr * R; e += kThreads) su[e] = (double)U[s0 * R + e];
-            __syncthreads();
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int k = 0; k < kGramEPT; ++k) {
-                const int e = e0 + threadIdx.x + k * kThreads;
-                if (e < R * R) {
-                    const int a = e / R, c = e % R;
-                    double sum = acc[k];
-                    for (int i = 0; i < nr; ++i) sum += su[i * R + a] * su[i * R + c];
-                    acc[k] = sum;
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int64_t s0 = i0; s0 < i1; s0 += SR) {
+        const int nr = (int)min((int64_t)SR, i1 - s0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * RP; e += kThreads) {
+            const int r = e / RP, col = e - r * RP;
+            su[e] = col < R ? (double)U[(s0 + r) * R + col] : 0.0;
+        }
+        __syncthreads();
+        if (own) {
+            for (int i = 0; i < nr; ++i) {
+                double va[4], vc[4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    va[x] = su[i * RP + a0 + x];
+                    vc[x] = su[i * RP + c0 + x];
                 }
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] += va[x] * vc[y];
             }
         }
-#pragma unroll
-        for (int k = 0; k < kGramEPT; ++k) {
-            const int e = e0 + threadIdx.x + k * kThreads;
-            if (e < R * R) dst[e] = acc[k];
-        }
     }
+    if (!own) return;
+    double *dst = part + (int64_t)blockIdx.x * R * R;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+            if (a0 + x < R && c0 + y < R) dst[(a0 + x) * R + c0 + y] = acc[x][y];
 }
 
 // out[e] = sum_{b < nslices} part[b][e], in slice order.
@@ -185,18 +198,28 @@ __global__ __launch_bounds__(kThreads) void k_restore_if_failed(const int *__res
         dst[e] = snap[e];
 }
 
-// grad[i][c] = sum_d U[i][d] H[d][c] - M[i][c], in float64.
+// grad[i][c] = sum_d U[i][d] H[d][c] - M[i][c], in float64.  A work-group
+// owns 64 consecutive outputs (one per lane); its 4 waves take the four
+// quarters of the d range and their sums are added in wave order.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_grad(const T *__restrict__ U, const double *__restrict__ H,
                                                    const T *__restrict__ M, int64_t In, int R,
                                                    T *__restrict__ G) {
-    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= In * R) return;
-    const int64_t i = e / R;
-    const int c = (int)(e % R);
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    const int q = (R + 3) / 4;
+    const int d0 = wave * q, d1 = min(R, d0 + q);
     double s = 0.0;
-    for (int d = 0; d < R; ++d) s += (double)U[i * R + d] * H[d * R + c];
-    G[e] = (T)(s - (double)M[e]);
+    if (e < In * R) {
+        const int64_t i = e / R;
+        const int c = (int)(e % R);
+        for (int d = d0; d < d1; ++d) s += (double)U[i * R + d] * H[d * R + c];
+    }
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && e < In * R)
+        G[e] = (T)((((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]) - (double)M[e]);
 }
 
 // Fixed-order block sum of 256 per-thread doubles; valid in thread 0.
@@ -225,24 +248,33 @@ __global__ __launch_bounds__(kThreads) void k_dot_partial(const T *__restrict__ 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// f = 1/2 (||X||^2 - 2 <M_{N-1}, U_{N-1}> + sum_ab prod_k G_k[a][b]); with
-// want_fit the result is 1 - sqrt(max(0, 2 f)) / sqrt(||X||^2) instead.
-__global__ __launch_bounds__(kThreads) void k_loss(const double *__restrict__ xnorm2,
-                                                   const double *__restrict__ inner,
-                                                   const double *__restrict__ grams, int N, int R,
-                                                   int want_fit, double *__restrict__ out) {
+// part[block] = sum over the block's grid-stride share of the entries e of
+// prod_k G_k[e] (the Hadamard product of all Grams), in float64: a fixed
+// split, added in order by k_loss.
+__global__ __launch_bounds__(kThreads) void k_hadsum_partial(const double *__restrict__ grams, int N, int R,
+                                                             double *__restrict__ part) {
     __shared__ double sh[kThreads];
+    const int64_t RR = (int64_t)R * R;
     double s = 0.0;
-    for (int e = threadIdx.x; e < R * R; e += kThreads) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < RR; e += (int64_t)gridDim.x * kThreads) {
         double v = 1.0;
-        for (int k = 0; k < N; ++k) v *= grams[(int64_t)k * R * R + e];
+        for (int k = 0; k < N; ++k) v *= grams[k * RR + e];
         s += v;
     }
     s = block_sum(s, sh);
-    if (threadIdx.x == 0) {
-        const double f = 0.5 * (*xnorm2 - 2.0 * *inner + s);
-        *out = want_fit ? 1.0 - sqrt(fmax(0.0, 2.0 * f)) / sqrt(*xnorm2) : f;
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// f = 1/2 (||X||^2 - 2 <M_{N-1}, U_{N-1}> + sum_ab prod_k G_k[a][b]), the
+// last sum given as nparts partial sums; with want_fit the result is
+// 1 - sqrt(max(0, 2 f)) / sqrt(||X||^2) instead.
+__global__ void k_loss(const double *__restrict__ xnorm2, const double *__restrict__ inner,
+                       const double *__restrict__ hpart, int nparts, int want_fit, double *__restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += hpart[b];
+    const double f = 0.5 * (*xnorm2 - 2.0 * *inner + s);
+    *out = want_fit ? 1.0 - sqrt(fmax(0.0, 2.0 * f)) / sqrt(*xnorm2) : f;
 }
 
 // Per-block partial sums of squares of the tensor entries (bf16 pairs are

@@ -14,6 +14,7 @@
 #include "bf16_kernels.hpp"
 #include "mttkrp32_kernels.hpp"
 #include "mttkrp_kernels.hpp"
+#include "tree_kernels.hpp"
 
 using namespace cpm;
 
@@ -197,7 +198,10 @@ constexpr int64_t kF32Chunk = 128;  // inner entries per work-group (tile of 16 
 constexpr int kF32GroupsLeft = 768;   // three resident work-groups per CU
 constexpr int kF32GroupsRight = 512;  // two (its cross-wave reduction takes 16 KB of LDS per j)
 
-bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *X) {
+// tight: the inner contracted group grows only while it still fits one
+// chunk (at least one mode), so the contracted range is not cut into chunks
+// whose partial results are each a whole output; used for wide outputs.
+bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *X, bool tight) {
     const int nct = (R + 31) / 32;
     const bool left = p.IL >= 32;
     const int ncmax = left ? 4 : 2;
@@ -209,7 +213,12 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.kind = kLeft32;
         int q = 0;
         p.G_in = 1;
-        while (q < mode && p.G_in < kF32Chunk) p.G_in *= dims[q++];
+        if (tight) {
+            p.G_in = dims[q++];
+            while (q < mode && p.G_in * dims[q] <= kF32Chunk) p.G_in *= dims[q++];
+        } else {
+            while (q < mode && p.G_in < kF32Chunk) p.G_in *= dims[q++];
+        }
         if (p.G_in % 4 != 0 || xa % 16 != 0) return false;  // rows need 16-byte loads
         p.p = q;
         p.G_out = p.IL / p.G_in;
@@ -241,7 +250,12 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         const int64_t lcap = kF32Chunk;
         int q = mode + 1;
         p.G_in = 1;
-        while (q < N && p.G_in < lcap) p.G_in *= dims[q++];
+        if (tight && q < N) {
+            p.G_in = dims[q++];
+            while (q < N && p.G_in * dims[q] <= lcap) p.G_in *= dims[q++];
+        } else {
+            while (q < N && p.G_in < lcap) p.G_in *= dims[q++];
+        }
         p.p = q;
         p.n_outer = p.IR / p.G_in;
         const int64_t lcmax = std::max<int64_t>(unit, lcap / unit * unit);
@@ -280,7 +294,18 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
     }
     if (dt == CPM_F32) {
         Plan q = p;
-        if (plan_f32(q, dims, N, R, mode, X) && q.max_offset < kMaxBufferOffset) return q;
+        if (plan_f32(q, dims, N, R, mode, X, false) && q.max_offset < kMaxBufferOffset) {
+            // Split-K partials that rival X itself (a wide output, as in a
+            // partial contraction over a few modes): prefer the tight inner
+            // group when it writes fewer of them.
+            if ((int64_t)q.partial_bytes > p.IL * p.In * p.IR / 2) {
+                Plan t = p;
+                if (plan_f32(t, dims, N, R, mode, X, true) && t.max_offset < kMaxBufferOffset &&
+                    t.partial_bytes < q.partial_bytes)
+                    return t;
+            }
+            return q;
+        }
     }
     const bool left = p.IL >= 16;
     const bool dbl = dt == CPM_F64;
@@ -706,12 +731,184 @@ size_t max_mttkrp_ws(const int64_t *dims, int N, int R, cpm_dtype dt) {
     return m;
 }
 
+// ------------------- all-mode MTTKRP with cross-mode reuse ------------------
+// Modes split into [0, s) and [s, N).  Pass A contracts the right group:
+// X viewed as (L, I_s, ..., I_{N-1}) with L = I_0 ... I_{s-1}, mode 0, gives
+// T_L (L x R).  Pass B contracts the left group: X viewed as (I_0, ...,
+// I_{s-1}, Rr), mode s, gives T_R (Rr x R).  Each mode's MTTKRP is then a
+// leaf of its group's intermediate (k_tree_leaf).  Used from N = 4 on, and
+// only while the intermediates (written once, read by every leaf of their
+// group) move fewer entries than one pass over X.
+struct TreePlan {
+    bool use = false;
+    int s = 0, nA = 0, nB = 0;
+    int64_t L = 1, Rr = 1;
+    int64_t dA[CPM_MAX_MODES], dB[CPM_MAX_MODES];
+};
+
+TreePlan plan_tree(const int64_t *dims, int N, int R) {
+    TreePlan t{};
+    if (N < 4) return t;
+    int64_t I = 1;
+    for (int k = 0; k < N; ++k) I *= dims[k];
+    double best = 0.0;
+    int bs = 0;
+    int64_t L = 1;
+    for (int s = 1; s < N; ++s) {
+        L *= dims[s - 1];
+        const int64_t Rr = I / L;
+        const double cost = ((double)L * (1 + s) + (double)Rr * (1 + N - s)) * R;
+        if (bs == 0 || cost < best) {
+            best = cost;
+            bs = s;
+        }
+    }
+    if (best > (double)I) return t;
+    t.use = true;
+    t.s = bs;
+    for (int k = 0; k < bs; ++k) t.L *= dims[k];
+    t.Rr = I / t.L;
+    t.nA = N - bs + 1;
+    t.dA[0] = t.L;
+    for (int k = bs; k < N; ++k) t.dA[k - bs + 1] = dims[k];
+    t.nB = bs + 1;
+    for (int k = 0; k < bs; ++k) t.dB[k] = dims[k];
+    t.dB[bs] = t.Rr;
+    return t;
+}
+
+bool tree_reach_ok(const TreePlan &t, const void *X, int R, cpm_dtype dt) {
+    return make_plan(t.dA, t.nA, R, 0, dt, X).max_offset < kMaxBufferOffset &&
+           make_plan(t.dB, t.nB, R, t.s, dt, X).max_offset < kMaxBufferOffset;
+}
+
+// Leaf launch shape for mode t of a group with dims g[0..m).
+constexpr int64_t kLeafBlocks = 4096;
+constexpr int64_t kLeafMinPairs = 256;
+constexpr int64_t kLeafMaxRowBlocks = 65536;
+struct LeafShape {
+    int64_t Ll, It, pairs, per_split, S, xblocks;
+    int rc_shift, ncb;
+};
+
+LeafShape leaf_shape(const int64_t *g, int m, int t, int R) {
+    LeafShape q{};
+    q.Ll = 1;
+    for (int k = 0; k < t; ++k) q.Ll *= g[k];
+    q.It = g[t];
+    int64_t Lr = 1;
+    for (int k = t + 1; k < m; ++k) Lr *= g[k];
+    q.pairs = q.Ll * Lr;
+    const int RC = R >= 64 ? 64 : pow2_at_least(R);
+    q.rc_shift = 0;
+    while ((1 << q.rc_shift) < RC) ++q.rc_shift;
+    q.ncb = (int)ceil_div(R, RC);
+    q.xblocks = std::min(q.It, kLeafMaxRowBlocks);
+    int64_t S = ceil_div(kLeafBlocks, q.xblocks * q.ncb);
+    S = std::max<int64_t>(1, std::min(S, ceil_div(q.pairs, kLeafMinPairs)));
+    q.per_split = ceil_div(q.pairs, S);
+    q.S = ceil_div(q.pairs, q.per_split);
+    return q;
+}
+
+size_t leaf_partial_bytes(const int64_t *dims, int N, int R, cpm_dtype dt, const TreePlan &t) {
+    size_t b = 0;
+    for (int n = 0; n < N; ++n) {
+        const int g0 = n < t.s ? 0 : t.s, g1 = n < t.s ? t.s : N;
+        const LeafShape q = leaf_shape(dims + g0, g1 - g0, n - g0, R);
+        if (q.S > 1) b = std::max(b, (size_t)q.S * q.It * R * dtype_f_bytes(dt));
+    }
+    return b;
+}
+
+struct AllWs {
+    void *TL, *TR, *leaf, *mws;
+    size_t need;
+};
+
+// Workspace of the all-mode MTTKRP, carved from base + off (sizes only when
+// base is null): the intermediates, the leaf partials and the workspace of
+// the largest single MTTKRP (per mode, or either pass).
+AllWs layout_all(const int64_t *dims, int N, int R, cpm_dtype dt, char *base, size_t off) {
+    AllWs w{};
+    const size_t start = off;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const TreePlan t = plan_tree(dims, N, R);
+    size_t m = max_mttkrp_ws(dims, N, R, dt);
+    if (t.use) {
+        const size_t fz = dtype_f_bytes(dt);
+        w.TL = take((size_t)t.L * R * fz);
+        w.TR = take((size_t)t.Rr * R * fz);
+        w.leaf = take(leaf_partial_bytes(dims, N, R, dt, t));
+        m = std::max(m, mttkrp_ws(t.dA, t.nA, R, 0, dt));
+        m = std::max(m, mttkrp_ws(t.dB, t.nB, R, t.s, dt));
+    }
+    w.mws = take(m);
+    w.need = off - start;
+    return w;
+}
+
+// Pass A (left = true: T_L from the right group's factors) or pass B.
+cpm_status tree_pass(const TreePlan &t, bool left, const void *X, const void *const *factors, int R, cpm_dtype dt,
+                     const AllWs &w, hipStream_t st) {
+    const void *f[CPM_MAX_MODES];
+    if (left) {
+        const int N = t.nA + t.s - 1;
+        f[0] = nullptr;
+        for (int k = t.s; k < N; ++k) f[k - t.s + 1] = factors[k];
+        const Plan p = make_plan(t.dA, t.nA, R, 0, dt, X);
+        return run_mttkrp(p, X, t.dA, t.nA, f, R, 0, w.TL, dt, w.mws, st);
+    }
+    for (int k = 0; k < t.s; ++k) f[k] = factors[k];
+    f[t.s] = nullptr;
+    const Plan p = make_plan(t.dB, t.nB, R, t.s, dt, X);
+    return run_mttkrp(p, X, t.dB, t.nB, f, R, t.s, w.TR, dt, w.mws, st);
+}
+
+template <typename T>
+cpm_status tree_leaf_t(const TreePlan &t, const int64_t *dims, int N, const void *const *factors, int R, int n,
+                       const AllWs &w, T *out, hipStream_t st) {
+    const bool left = n < t.s;
+    const int g0 = left ? 0 : t.s, g1 = left ? t.s : N;
+    // the group's other modes in order: the pair index q = b + Ll * a runs
+    // over their Khatri-Rao product, first mode fastest
+    int om[CPM_MAX_MODES];
+    int no = 0;
+    for (int k = g0; k < g1; ++k)
+        if (k != n) om[no++] = k;
+    const Krp<T> kk = krp_of<T>(factors, dims, om, no);
+    const LeafShape q = leaf_shape(dims + g0, g1 - g0, n - g0, R);
+    const T *Tm = reinterpret_cast<const T *>(left ? w.TL : w.TR);
+    T *dst = q.S > 1 ? reinterpret_cast<T *>(w.leaf) : out;
+    hipLaunchKernelGGL(k_tree_leaf<T>, dim3((unsigned)q.xblocks, (unsigned)q.S, (unsigned)q.ncb), dim3(kThreads), 0,
+                       st, Tm, q.Ll, q.It, q.pairs, q.per_split, kk, R, q.rc_shift, dst);
+    LAUNCH_CHECK("k_tree_leaf");
+    if (q.S > 1) {
+        const Krp<T> none{};
+        hipLaunchKernelGGL((k_reduce<T, T>), dim3((unsigned)ceil_div(q.It * R, 64)), dim3(kThreads), 0, st, dst,
+                           q.S, q.It, q.It, (int64_t)1, none, R, out);
+        LAUNCH_CHECK("k_reduce");
+    }
+    return CPM_OK;
+}
+
+cpm_status tree_leaf(const TreePlan &t, const int64_t *dims, int N, const void *const *factors, int R, int n,
+                     cpm_dtype dt, const AllWs &w, void *out, hipStream_t st) {
+    if (dt == CPM_F64) return tree_leaf_t<double>(t, dims, N, factors, R, n, w, (double *)out, st);
+    return tree_leaf_t<float>(t, dims, N, factors, R, n, w, (float *)out, st);
+}
+
 // ---------------------------- ALS / gradient -------------------------------
 struct SolveWs {
     int *status;
     double *xnorm2, *inner, *result;
-    double *grams, *gpart, *H, *L, *Lt;
-    void *M, *snap, *mws, *sumsq;
+    double *grams, *gpart, *H, *L, *Lt, *hpart;
+    void *M, *snap, *sumsq;
+    AllWs all;  // intermediates of the all-mode MTTKRP and the MTTKRP workspace
     size_t need;
 };
 
@@ -720,6 +917,18 @@ constexpr int64_t kGramRows = 32;
 constexpr int64_t kGramBlocks = 64;
 int64_t gram_blocks(int64_t I) { return std::min(kGramBlocks, ceil_div(I, kGramRows)); }
 constexpr int kSumsqBlocks = 1024;
+constexpr int kHadsumBlocks = 64;
+
+// f (or the fit) from ||X||^2, <M_{N-1}, U_{N-1}> and the Grams.
+cpm_status loss_enqueue(const double *xnorm2, const double *inner, const double *grams, int N, int R,
+                        double *hpart, int want_fit, double *out, hipStream_t st) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kHadsumBlocks, ceil_div((int64_t)R * R, kThreads)));
+    hipLaunchKernelGGL(k_hadsum_partial, dim3(blocks), dim3(kThreads), 0, st, grams, N, R, hpart);
+    LAUNCH_CHECK("k_hadsum_partial");
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, st, xnorm2, inner, hpart, blocks, want_fit, out);
+    LAUNCH_CHECK("k_loss");
+    return CPM_OK;
+}
 
 SolveWs layout_solve(const int64_t *dims, int N, int R, cpm_dtype dt, char *base, bool snapshot) {
     SolveWs w{};
@@ -745,11 +954,12 @@ SolveWs layout_solve(const int64_t *dims, int N, int R, cpm_dtype dt, char *base
     w.H = (double *)take((size_t)R * R * sizeof(double));
     w.L = (double *)take((size_t)R * R * sizeof(double));
     w.Lt = (double *)take((size_t)R * R * sizeof(double));
+    w.hpart = (double *)take((size_t)kHadsumBlocks * sizeof(double));
     w.M = take((size_t)maxI * R * fz);
     w.snap = snapshot ? take((size_t)sumI * R * fz) : nullptr;
     w.sumsq = take((size_t)kSumsqBlocks * sizeof(double));
-    w.mws = take(max_mttkrp_ws(dims, N, R, dt));
-    w.need = off;
+    w.all = layout_all(dims, N, R, dt, base, off);
+    w.need = off + w.all.need;
     return w;
 }
 
@@ -757,7 +967,10 @@ template <typename T>
 cpm_status gram_t(const T *U, int64_t I, int R, double *gpart, double *G, hipStream_t st) {
     const int64_t blocks = gram_blocks(I);
     const int64_t rows = ceil_div(I, blocks);
-    hipLaunchKernelGGL((k_gram_partial<T>), dim3((unsigned)blocks), dim3(kThreads), 0, st, U, I, R, rows, gpart);
+    const int tr = (R + 3) / 4;
+    const unsigned tiles = (unsigned)ceil_div((int64_t)tr * tr, kThreads);
+    hipLaunchKernelGGL((k_gram_partial<T>), dim3((unsigned)blocks, tiles), dim3(kThreads), 0, st, U, I, R, rows,
+                       gpart);
     LAUNCH_CHECK("k_gram_partial");
     hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)ceil_div((int64_t)R * R, kThreads)), dim3(kThreads), 0, st,
                        gpart, blocks, (int64_t)R * R, G);
@@ -855,6 +1068,66 @@ cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *
     return run_mttkrp(p, X, dims, N, factors, R, mode, out, dt, workspace, stream);
 }
 
+size_t cpm_mttkrp_all_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {
+    int64_t total;
+    std::string saved = g_last_error;
+    if (check_dtype(dt) || check_shape(dims, N, R, &total, CPM_MAX_RANK)) {
+        g_last_error = saved;
+        return 0;
+    }
+    return layout_all(dims, N, R, dt, nullptr, 0).need;
+}
+
+cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                      void *const *outs, cpm_dtype dt, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    int64_t total;
+    cpm_status s = check_dtype(dt);
+    if (s) return s;
+    s = check_shape(dims, N, R, &total, CPM_MAX_RANK);
+    if (s) return s;
+    if (!X) return fail(CPM_EINVAL, "X is null");
+    if (!factors) return fail(CPM_EINVAL, "factors is null");
+    if (!outs) return fail(CPM_EINVAL, "outs is null");
+    for (int k = 0; k < N; ++k)
+        if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    const size_t need = layout_all(dims, N, R, dt, nullptr, 0).need;
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    s = check_reach(X, dims, N, R, dt);
+    if (s) return s;
+    const AllWs w = layout_all(dims, N, R, dt, (char *)workspace, 0);
+    int nwant = 0;
+    bool want_left = false, want_right = false;
+    TreePlan tree = plan_tree(dims, N, R);
+    for (int n = 0; n < N; ++n)
+        if (outs[n]) {
+            ++nwant;
+            (n < tree.s ? want_left : want_right) = true;
+        }
+    tree.use = tree.use && nwant >= 3 && tree_reach_ok(tree, X, R, dt);
+    if (tree.use) {
+        if (want_left) {
+            s = tree_pass(tree, true, X, factors, R, dt, w, stream);
+            if (s) return s;
+        }
+        if (want_right) {
+            s = tree_pass(tree, false, X, factors, R, dt, w, stream);
+            if (s) return s;
+        }
+    }
+    for (int n = 0; n < N; ++n) {
+        if (!outs[n]) continue;
+        if (tree.use) {
+            s = tree_leaf(tree, dims, N, factors, R, n, dt, w, outs[n], stream);
+        } else {
+            const Plan p = make_plan(dims, N, R, n, dt, X);
+            s = run_mttkrp(p, X, dims, N, factors, R, n, outs[n], dt, w.mws, stream);
+        }
+        if (s) return s;
+    }
+    return CPM_OK;
+}
+
 size_t cpm_cp_als_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {
     int64_t total;
     std::string saved = g_last_error;
@@ -909,9 +1182,23 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
         if (s) return s;
     }
     const size_t lds_chol = (size_t)R * R * sizeof(double);
+    // With the cross-mode reuse, T_L depends only on the right group's
+    // factors, which are not updated before mode s, and T_R is formed after
+    // the left group's updates: the sweep stays Gauss-Seidel.
+    TreePlan tree = plan_tree(dims, N, R);
+    tree.use = tree.use && tree_reach_ok(tree, X, R, dt);
+    const void *const *cf = (const void *const *)factors;
     for (int n = 0; n < N; ++n) {
-        Plan p = make_plan(dims, N, R, n, dt, X);
-        s = run_mttkrp(p, X, dims, N, (const void *const *)factors, R, n, w.M, dt, w.mws, stream);
+        if (tree.use) {
+            if (n == 0 || n == tree.s) {
+                s = tree_pass(tree, n == 0, X, cf, R, dt, w.all, stream);
+                if (s) return s;
+            }
+            s = tree_leaf(tree, dims, N, cf, R, n, dt, w.all, w.M, stream);
+        } else {
+            Plan p = make_plan(dims, N, R, n, dt, X);
+            s = run_mttkrp(p, X, dims, N, cf, R, n, w.M, dt, w.all.mws, stream);
+        }
         if (s) return s;
         s = hadamard_except(w.grams, N, R, n, w.H, stream);
         if (s) return s;
@@ -954,9 +1241,8 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
         }
         s = dot_enqueue(w.M, factors[N - 1], dims[N - 1] * R, dt, (double *)w.sumsq, w.inner, stream);
         if (s) return s;
-        hipLaunchKernelGGL(k_loss, dim3(1), dim3(kThreads), 0, stream, w.xnorm2, w.inner, w.grams, N, R, 1,
-                           w.result);
-        LAUNCH_CHECK("k_loss");
+        s = loss_enqueue(w.xnorm2, w.inner, w.grams, N, R, w.hpart, 1, w.result, stream);
+        if (s) return s;
     }
     off = 0;
     for (int k = 0; k < N; ++k) {
@@ -1003,12 +1289,37 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
         s = gram(factors[k], dims[k], R, dt, w.gpart, w.grams + (size_t)k * R * R, stream);
         if (s) return s;
     }
+    auto wanted = [&](int n) { return (grads && grads[n]) || (loss_dev && n == N - 1); };
+    int nwant = 0;
+    bool want_left = false, want_right = false;
+    TreePlan tree = plan_tree(dims, N, R);
+    for (int n = 0; n < N; ++n)
+        if (wanted(n)) {
+            ++nwant;
+            (n < tree.s ? want_left : want_right) = true;
+        }
+    // the reuse pays once three or more modes are wanted
+    tree.use = tree.use && nwant >= 3 && tree_reach_ok(tree, X, R, dt);
+    if (tree.use) {
+        if (want_left) {
+            s = tree_pass(tree, true, X, factors, R, dt, w.all, stream);
+            if (s) return s;
+        }
+        if (want_right) {
+            s = tree_pass(tree, false, X, factors, R, dt, w.all, stream);
+            if (s) return s;
+        }
+    }
     for (int n = 0; n < N; ++n) {
         const bool want_grad = grads && grads[n];
         const bool want_inner = loss_dev && n == N - 1;
         if (!want_grad && !want_inner) continue;
-        Plan p = make_plan(dims, N, R, n, dt, X);
-        s = run_mttkrp(p, X, dims, N, factors, R, n, w.M, dt, w.mws, stream);
+        if (tree.use) {
+            s = tree_leaf(tree, dims, N, factors, R, n, dt, w.all, w.M, stream);
+        } else {
+            Plan p = make_plan(dims, N, R, n, dt, X);
+            s = run_mttkrp(p, X, dims, N, factors, R, n, w.M, dt, w.all.mws, stream);
+        }
         if (s) return s;
         if (want_inner) {
             s = dot_enqueue(w.M, factors[n], dims[n] * R, dt, (double *)w.sumsq, w.inner, stream);
@@ -1017,7 +1328,7 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
         if (want_grad) {
             s = hadamard_except(w.grams, N, R, n, w.H, stream);
             if (s) return s;
-            const unsigned blocks = (unsigned)ceil_div(dims[n] * R, kThreads);
+            const unsigned blocks = (unsigned)ceil_div(dims[n] * R, 64);
             if (dt == CPM_F64)
                 hipLaunchKernelGGL(k_grad<double>, dim3(blocks), dim3(kThreads), 0, stream,
                                    (const double *)factors[n], w.H, (const double *)w.M, dims[n], R,
@@ -1036,9 +1347,8 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
             s = xnorm2_enqueue(X, total, dt, (double *)w.sumsq, w.xnorm2, stream);
             if (s) return s;
         }
-        hipLaunchKernelGGL(k_loss, dim3(1), dim3(kThreads), 0, stream, w.xnorm2, w.inner, w.grams, N, R, 0,
-                           loss_dev);
-        LAUNCH_CHECK("k_loss");
+        s = loss_enqueue(w.xnorm2, w.inner, w.grams, N, R, w.hpart, 0, loss_dev, stream);
+        if (s) return s;
     }
     return CPM_OK;
 }

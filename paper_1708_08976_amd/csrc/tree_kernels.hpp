@@ -1,0 +1,122 @@
+// Last step of the all-mode MTTKRP with cross-mode reuse (the reuse of
+// partial results across the MTTKRPs of different modes that the paper's
+// Conclusion names as the next step, after Phan et al., Section III.C).
+//
+// The modes are split into two groups, [0, s) and [s, N).  One pass over X
+// contracts the right group (an external-mode MTTKRP of X viewed as
+// (I_0 ... I_{s-1} flattened, I_s, ..., I_{N-1})), leaving
+//   T_L(l, c) = sum_r X(l, r) K_R(r, c)      l over the left group's entries,
+// and one pass contracts the left group the same way, leaving T_R(r, c).
+// Every mode's MTTKRP then follows from the intermediate of its own group:
+//   M_n(i, c) = sum over l with l_n = i of T(l, c) * prod_{k in group, k != n} U_k(l_k, c),
+// which is the MTTKRP definition with the other group's sum already done.
+// This file holds that last step; the two passes are ordinary MTTKRP
+// launches.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace cpm {
+
+// Product of factors 1..Z-1 of a Khatri-Rao descriptor at row g (all but
+// the fastest), digits decoded with 32-bit division when the operands allow.
+template <typename T>
+__device__ inline T krp_slow_value(const Krp<T> &k, int R, int64_t g, int c) {
+    T v = T(1);
+    for (int z = 1; z < k.Z; ++z) v *= k.U[z][mod64(div64(g, k.stride[z]), k.J[z]) * R + c];
+    return v;
+}
+
+// One group mode's MTTKRP from the group intermediate T (rows of R values;
+// the row index is the group's multi-index, first mode fastest).  Writing a
+// row as l = b + Ll * (i + It * a) (b over the group modes before this one,
+// a over those after), and q = b + Ll * a for the pair, M(i, c) = sum_q
+// T(l, c) K(q, c), with K the Khatri-Rao product of the group's other
+// modes in order (descriptor kk).
+//
+// grid.x strides over the It output rows, grid.y splits the pairs into
+// ranges of per_split, grid.z takes blocks of 2^rc_shift rank columns.
+// Within a wave, 64 >> rc_shift sub-rows run side by side; each of the
+// block's 4 * (64 >> rc_shift) sub-rows walks a contiguous run of pairs as
+// Algorithm 1 walks Khatri-Rao rows: the product of the slower factors is
+// held and refreshed only when the fastest index wraps, and the T row
+// advances by one (by Ll * (It - 1) more when b wraps).  The block's sum is
+// formed in LDS in a fixed order (waves, then sub-rows), in float64.  With
+// grid.y == 1 the result goes to M directly, otherwise to slice blockIdx.y
+// of the partial buffer [grid.y][It][R], summed afterwards in slice order.
+constexpr int kLeafBatch = 8;
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_tree_leaf(const T *__restrict__ Tm, int64_t Ll, int64_t It,
+                                                        int64_t pairs, int64_t per_split, Krp<T> kk, int R,
+                                                        int rc_shift, T *__restrict__ out) {
+    __shared__ double red[kThreads];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int RC = 1 << rc_shift;
+    const int subs = 64 >> rc_shift;
+    const int sub = lane >> rc_shift;
+    const int c = (int)blockIdx.z * RC + (lane & (RC - 1));
+    const bool col_ok = c < R;
+    const int cc = col_ok ? c : 0;
+    const int64_t p0 = (int64_t)blockIdx.y * per_split;
+    const int64_t p1 = p0 + per_split < pairs ? p0 + per_split : pairs;
+    const int workers = 4 * subs;
+    const int64_t run = (p1 - p0 + workers - 1) / workers;
+    const int64_t wk = wave * subs + sub;
+    const int64_t q0 = p0 + wk * run < p1 ? p0 + wk * run : p1;
+    const int64_t q1 = q0 + run < p1 ? q0 + run : p1;
+    const int64_t J0 = kk.Z > 0 ? kk.J[0] : 1;
+    const T *U0 = kk.Z > 0 ? kk.U[0] : nullptr;
+    for (int64_t i = blockIdx.x; i < It; i += gridDim.x) {
+        double acc = 0.0;
+        if (q0 < q1) {
+            const int64_t a = div64(q0, Ll);
+            int64_t b = q0 - a * Ll;
+            int64_t row = b + Ll * (i + It * a);
+            int64_t d0 = kk.Z > 0 ? mod64(q0, J0) : 0;
+            T slow = krp_slow_value(kk, R, q0, cc);
+            // kLeafBatch pairs per step: rows and weights first, then the
+            // loads of all of them in flight together, then the adds in
+            // pair order
+            for (int64_t q = q0; q < q1; q += kLeafBatch) {
+                int64_t rows[kLeafBatch];
+                T ws[kLeafBatch];
+#pragma unroll
+                for (int u = 0; u < kLeafBatch; ++u) {
+                    const bool ok = q + u < q1;
+                    rows[u] = ok ? row : -1;
+                    ws[u] = ok ? (kk.Z > 0 ? slow * U0[d0 * R + cc] : T(1)) : T(0);
+                    if (ok) {
+                        ++row;
+                        if (++b == Ll) {
+                            b = 0;
+                            row += Ll * (It - 1);
+                        }
+                        if (++d0 == J0) {
+                            d0 = 0;
+                            if (q + u + 1 < q1) slow = krp_slow_value(kk, R, q + u + 1, cc);
+                        }
+                    }
+                }
+                double v[kLeafBatch];
+#pragma unroll
+                for (int u = 0; u < kLeafBatch; ++u)
+                    v[u] = (col_ok && rows[u] >= 0) ? (double)Tm[rows[u] * R + c] : 0.0;
+#pragma unroll
+                for (int u = 0; u < kLeafBatch; ++u) acc += v[u] * (double)ws[u];
+            }
+        }
+        red[tid] = acc;
+        __syncthreads();
+        if (tid < RC) {
+            double s = 0.0;
+            for (int w = 0; w < 4; ++w)
+                for (int q = 0; q < subs; ++q) s += red[w * 64 + q * RC + tid];
+            const int oc = (int)blockIdx.z * RC + tid;
+            if (oc < R) out[((int64_t)blockIdx.y * It + i) * R + oc] = (T)s;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace cpm

@@ -104,3 +104,46 @@ def test_solver_entry_points_validate():
     assert lib.cpm_krp_rows(_ptrs(2), _dims((3, 4)), 2, 5, 10, 5, FAKE, 0, None) == _abi.CPM_EINVAL
     assert lib.cpm_krp_rows(_ptrs(2), _dims((3, 4)), 0, 5, 0, 5, FAKE, 0, None) == _abi.CPM_EINVAL
     assert lib.cpm_xnorm2(FAKE, d, 3, 0, FAKE, None, 0, None) == _abi.CPM_EWORKSPACE
+
+
+def call_mttkrp_all(dims, R=8, X=FAKE, dt=0, factors=None, outs=None, ws=None, ws_len=0):
+    lib = _abi.load()
+    N = len(dims)
+    f = factors if factors is not None else _ptrs(N)
+    o = outs if outs is not None else _ptrs(N)
+    return lib.mttkrp_all(X, _dims(dims), N, f, R, o, dt, ws, ws_len, None)
+
+
+def test_mttkrp_all_validates_before_launch():
+    lib = _abi.load()
+    d = (64,) * 5
+    assert call_mttkrp_all(d, X=None) == _abi.CPM_EINVAL
+    assert call_mttkrp_all(d, R=257) == _abi.CPM_EUNSUPPORTED
+    assert call_mttkrp_all(d, dt=9) == _abi.CPM_EINVAL
+    # every factor is read (each one belongs to some other mode's product)
+    assert call_mttkrp_all(d, factors=_ptrs(5, null_at=3)) == _abi.CPM_EINVAL
+    assert "factors[3]" in _abi.last_error()
+    assert lib.mttkrp_all(FAKE, _dims(d), 5, _ptrs(5), 8, None, 0, FAKE, 1 << 40, None) == _abi.CPM_EINVAL
+    need = _abi.mttkrp_all_workspace_bytes(d, 32, _abi.CPM_F32)
+    assert call_mttkrp_all(d, R=32, ws=None) == _abi.CPM_EWORKSPACE
+    assert call_mttkrp_all(d, R=32, ws=FAKE, ws_len=need - 1) == _abi.CPM_EWORKSPACE
+
+
+def test_mttkrp_all_workspace_holds_the_group_intermediates():
+    """64^5, R=32: the modes split 2 | 3, so the workspace holds the left
+    group's 64^2 x 32 and the right group's 64^3 x 32 float32 intermediates;
+    for a 3-way tensor each mode is an ordinary MTTKRP."""
+    d5 = (64,) * 5
+    inter = (64 ** 2 + 64 ** 3) * 32 * 4
+    ws5 = _abi.mttkrp_all_workspace_bytes(d5, 32, _abi.CPM_F32)
+    per_mode = max(_abi.mttkrp_workspace_bytes(d5, 32, n, _abi.CPM_F32) for n in range(5))
+    assert inter + per_mode <= ws5 <= inter + per_mode + (64 << 20)
+    assert _abi.mttkrp_all_workspace_bytes(d5, 32, _abi.CPM_F64) >= 2 * inter
+    d3 = (512, 512, 512)
+    assert _abi.mttkrp_all_workspace_bytes(d3, 32, _abi.CPM_F32) == max(
+        _abi.mttkrp_workspace_bytes(d3, 32, n, _abi.CPM_F32) for n in range(3))
+    # intermediates as large as X itself: no reuse, ordinary MTTKRPs
+    d = (2, 2, 2, 100000)
+    assert _abi.mttkrp_all_workspace_bytes(d, 32, _abi.CPM_F32) == max(
+        _abi.mttkrp_workspace_bytes(d, 32, n, _abi.CPM_F32) for n in range(4))
+    assert _abi.cp_grad_workspace_bytes(d5, 32, _abi.CPM_F32) >= inter

@@ -206,3 +206,21 @@ def test_config5_64p5_fp32_r128_sampled_rows():
     got = gpu_all_modes(X, dims, U)
     check_sampled(got, X.cpu().numpy().ravel(), dims, [u.cpu().numpy().astype(np.float64) for u in U], TOL["f32"],
                   "64^5 f32 R128")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
+def test_config5_64p5_mttkrp_all_with_reuse_sampled_rows(dtype):
+    """All five MTTKRPs of the 64^5 tensor from the two passes of the
+    cross-mode reuse (modes split 2 | 3), in the configuration the gradient
+    benchmark runs; sampled rows against the oracle."""
+    dims, R = (64,) * 5, 32
+    announce("64^5 mttkrp_all", dtype)
+    X, _ = inputs.noisy_low_rank(dims, 32, seed_factors=9, seed_noise=10, eta=0.05, device="cuda")
+    U = inputs.normal_factors(dims, R, seed=11, device="cuda")
+    code = _abi.CPM_F32 if dtype == "f32" else _abi.CPM_BF16X2
+    Xd = X if dtype == "f32" else _abi.split_bf16(X.reshape(-1))
+    outs = _abi.mttkrp_all(Xd, dims, U, dtype=code)
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in outs]
+    check_sampled(got, X.cpu().numpy().ravel(), dims, [u.cpu().numpy().astype(np.float64) for u in U],
+                  TOL[dtype], "64^5 mttkrp_all %s" % dtype)

@@ -1,0 +1,173 @@
+"""GPU parity of the all-mode MTTKRP with cross-mode reuse (mttkrp_all), and
+of cp_grad / cp_als_step, which form their MTTKRPs the same way from N = 4
+on, against the FP64 oracle.
+
+The reuse changes only the order of the sums (one group's modes contracted
+first, into an intermediate), so every mode must still meet the plain
+method's tolerance against the oracle's MTTKRP definition.  The shapes
+below are chosen so that the two-group scheme is taken (its intermediates
+show up in the workspace size, checked first), with ragged tiles in both
+passes and in the leaves, size-1 and size-2 modes, and several split points.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import TOL, announce, make_case, oracle_abs_all_modes, rel_err, rel_err_abs
+from oracle import oracle as O
+from paper_1708_08976_amd import _abi, inputs
+
+pytestmark = pytest.mark.gpu
+
+# (dims, ranks) with the reuse scheme taken at every listed rank
+TREE_CASES = [
+    ((20, 24, 22, 26), (1, 13, 32, 70)),
+    ((12, 12, 12, 12, 12), (1, 8, 32)),
+    ((33, 1, 40, 2, 50), (1, 5, 16)),
+    ((7, 6, 5, 4, 3, 2), (1, 3)),
+    ((64, 3, 5, 64), (1, 9, 20)),
+    ((3, 40, 37, 2, 9), (1, 7, 16)),
+]
+CODES = {"f32": _abi.CPM_F32, "f64": _abi.CPM_F64, "bf16x2": _abi.CPM_BF16X2}
+
+
+def uses_reuse(dims, R, code):
+    per_mode = max(_abi.mttkrp_workspace_bytes(dims, R, n, code) for n in range(len(dims)))
+    return _abi.mttkrp_all_workspace_bytes(dims, R, code) > per_mode
+
+
+def case_tensors(dims, R, seed, dtype):
+    if dtype == "f64":
+        X, U = make_case(dims, R, seed, dtype=torch.float64)
+        return X, U, X.cuda(), None
+    X, U = make_case(dims, R, seed)
+    if dtype == "f32":
+        return X, U, X.cuda(), None
+    planes = inputs.split_bf16_planes(X)
+    return X, U, planes.cuda(), planes
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16x2"])
+@pytest.mark.parametrize("dims,ranks", TREE_CASES)
+def test_mttkrp_all_matches_oracle(dims, ranks, dtype):
+    for R in ranks:
+        announce("mttkrp_all", dtype, dims, R)
+        code = CODES[dtype]
+        assert uses_reuse(dims, R, code), (dims, R)
+        X, U, Xd, planes = case_tensors(dims, R, seed=sum(dims) + R, dtype=dtype)
+        Ud = [u.cuda() for u in U]
+        outs = _abi.mttkrp_all(Xd, dims, Ud, dtype=code)
+        torch.cuda.synchronize()
+        if planes is None:
+            Xh, xt = X.numpy().ravel(), None
+        else:
+            Xh, xt = planes.numpy().view(np.uint16), O.BF16PAIR
+        Uh = [u.numpy() for u in U]
+        absr = oracle_abs_all_modes(X, dims, U)
+        for n in range(len(dims)):
+            ref = O.mttkrp(Xh, dims, Uh, n, xtype=xt)
+            got = outs[n].cpu().numpy()
+            assert np.isfinite(got).all(), n
+            err = rel_err_abs(got, ref, absr[n])
+            assert err <= TOL[dtype], (dims, R, n, err)
+
+
+def test_mttkrp_all_subsets_of_modes():
+    """Requested modes only; other outputs untouched.  Three or more modes
+    take the reuse scheme (with one or both passes), fewer are ordinary
+    MTTKRPs."""
+    dims, R = (20, 24, 22, 26), 13
+    X, U = make_case(dims, R, seed=3)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    Xh, Uh = X.numpy().ravel(), [u.numpy() for u in U]
+    for modes in [(0, 1, 2, 3), (0, 2, 3), (2, 3), (3,), (0, 1), (1, 2, 3), (0, 1, 3)]:
+        announce("subset", modes)
+        outs = [torch.full((d, R), 7.0, device="cuda") if n in modes else None for n, d in enumerate(dims)]
+        sentinel = [torch.full((d, R), 7.0, device="cuda") for d in dims]
+        outs_all = [o if o is not None else sentinel[n] for n, o in enumerate(outs)]
+        _abi.mttkrp_all(Xd, dims, Ud, outs=outs)
+        torch.cuda.synchronize()
+        for n in range(4):
+            if n in modes:
+                assert rel_err(outs_all[n].cpu().numpy(), O.mttkrp(Xh, dims, Uh, n)) <= TOL["f32"], (modes, n)
+            else:
+                assert bool((sentinel[n] == 7.0).all())
+
+
+def test_mttkrp_all_bitwise_reproducible():
+    dims, R = (20, 24, 22, 26), 32
+    X, U = make_case(dims, R, seed=4)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    a = _abi.mttkrp_all(Xd, dims, Ud)
+    b = _abi.mttkrp_all(Xd, dims, Ud)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("dims", [(40, 30, 20), (12, 12, 12, 12, 12)])
+def test_mttkrp_all_without_reuse_is_mttkrp(dims):
+    """A 3-way tensor, or a rank too large for the reuse to pay: every mode
+    is the ordinary MTTKRP, bit for bit."""
+    R = 16 if len(dims) == 3 else 70
+    assert not uses_reuse(dims, R, _abi.CPM_F32)
+    X, U = make_case(dims, R, seed=5)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    outs = _abi.mttkrp_all(Xd, dims, Ud)
+    for n in range(len(dims)):
+        assert torch.equal(outs[n], _abi.mttkrp(Xd, dims, Ud, n))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16x2"])
+@pytest.mark.parametrize("dims,R", [((20, 24, 22, 26), 32), ((33, 1, 40, 2, 50), 5), ((7, 6, 5, 4, 3, 2), 3)])
+def test_cp_grad_with_reuse_matches_oracle(dims, R, dtype):
+    code = CODES[dtype]
+    assert uses_reuse(dims, R, code)
+    announce("cp_grad reuse", dtype, dims, R)
+    X, U, Xd, planes = case_tensors(dims, R, seed=R + 11, dtype=dtype)
+    Ud = [u.cuda() for u in U]
+    Xh = X.numpy().ravel() if planes is None else planes.numpy().view(np.uint16)
+    xt = None if planes is None else O.BF16PAIR
+    Uh = [u.numpy().astype(np.float64) for u in U]
+    xn = O.xnorm2(Xh, dims, xtype=xt)
+    grads, loss = _abi.cp_grad(Xd, dims, Ud, xnorm2=xn, dtype=code)
+    torch.cuda.synchronize()
+    G, ld, _ = O.cp_grad(Xh, dims, Uh, xtype=xt)
+    tol = {"f32": TOL["f32"], "f64": 1e-11, "bf16x2": TOL["bf16x2"]}[dtype]
+    for n in range(len(dims)):
+        # scale: the two terms U_n H_n and M_n whose difference is the gradient
+        H = np.ones((R, R))
+        for k in range(len(dims)):
+            if k != n:
+                H *= Uh[k].T @ Uh[k]
+        scale = np.linalg.norm(Uh[n] @ H) + np.linalg.norm(G[n] + Uh[n] @ H)
+        err = np.linalg.norm(grads[n].cpu().numpy() - G[n]) / scale
+        assert err <= tol, (n, err)
+    assert abs(loss.item() - ld) <= (1e-12 if dtype == "f64" else 1e-5) * xn
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_als_sweep_with_reuse_matches_oracle(dtype):
+    """One Gauss-Seidel sweep: the left group's modes from the intermediate
+    formed before any update, the right group's from the one formed after
+    the left group's updates; against the oracle sweep."""
+    dims, R = (20, 24, 22, 26), 8
+    code = CODES[dtype]
+    assert uses_reuse(dims, R, code)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    X = inputs.uniform_tensor(dims, seed=21, dtype=tdt)
+    U = inputs.normal_factors(dims, R, seed=22, dtype=tdt)
+    Uh = [u.numpy().astype(np.float64) for u in U]
+    ref, fit_ref = O.cp_als_step(X.numpy().ravel(), dims, Uh)
+    kap = 1.0
+    for n in range(len(dims)):
+        H = np.ones((R, R))
+        for m in range(len(dims)):
+            if m != n:
+                H *= ref[m].T @ ref[m]
+        kap = max(kap, np.linalg.cond(H))
+    Ud = [u.cuda() for u in U]
+    fit = _abi.cp_als_step(X.cuda(), dims, Ud)
+    tol = 1e-10 if dtype == "f64" else 1e-5 * kap
+    for n, (g, r) in enumerate(zip(Ud, ref)):
+        assert rel_err(g.cpu().numpy(), r) <= tol, (n, rel_err(g.cpu().numpy(), r), tol)
+    assert fit == pytest.approx(fit_ref, abs=1e-10 if dtype == "f64" else 1e-5)
