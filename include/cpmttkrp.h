@@ -129,6 +129,27 @@ cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *con
                       void *const *outs, cpm_dtype dt, void *workspace, size_t ws_bytes,
                       hipStream_t stream);
 
+/*
+ * Bytes of workspace `cpm_residual2` needs (0 for invalid arguments).
+ */
+size_t cpm_residual2_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);
+
+/*
+ * *out_dev = ||X - [[U_0..U_{N-1}]]||_F^2 (device double), with every model
+ * entry sum_c prod_k U_k(i_k, c) (the CP model of Section 2.2) recomputed on
+ * the fly while X streams past once; nothing of the residual is stored.
+ * The Conclusion names this computation as the next bottleneck once MTTKRP
+ * is fast.  Unlike the identity ||X||^2 - 2 <M, U> + sum(Hadamard of
+ * Grams), it does not lose digits to cancellation when the model fits well:
+ * model entries are float32 sums of float32 products, differences and
+ * squares are summed in float64.  dt: CPM_F32 or CPM_BF16X2 (CPM_F64 gives
+ * CPM_EUNSUPPORTED).  factors: every entry read.  R <= 128.  The sum runs
+ * in a fixed order (bitwise reproducible).  Stream-ordered.
+ */
+cpm_status cpm_residual2(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                         cpm_dtype dt, double *out_dev, void *workspace, size_t ws_bytes,
+                         hipStream_t stream);
+
 /* Bytes of workspace for cp_als_step / cp_grad. */
 size_t cpm_cp_als_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);
 size_t cpm_cp_grad_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);

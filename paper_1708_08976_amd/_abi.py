@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_EUNSUPPORTED", 3: "CPM_ENO
 
 EXPORTS = ["cpm_version", "cpm_last_error", "cpm_mttkrp_workspace_bytes", "mttkrp",
            "cpm_mttkrp_all_workspace_bytes", "mttkrp_all",
+           "cpm_residual2_workspace_bytes", "cpm_residual2",
            "cpm_cp_als_workspace_bytes", "cpm_cp_grad_workspace_bytes", "cp_als_step", "cp_grad",
            "cpm_xnorm2_workspace_bytes", "cpm_xnorm2", "cpm_split_bf16", "cpm_krp_rows"]
 
@@ -54,6 +55,10 @@ def load():
     lib.cpm_mttkrp_all_workspace_bytes.restype = sz
     lib.mttkrp_all.argtypes = [vp, i64p, ci, vpp, ci, vpp, ci, vp, sz, vp]
     lib.mttkrp_all.restype = ci
+    lib.cpm_residual2_workspace_bytes.argtypes = [i64p, ci, ci, ci]
+    lib.cpm_residual2_workspace_bytes.restype = sz
+    lib.cpm_residual2.argtypes = [vp, i64p, ci, vpp, ci, ci, vp, vp, sz, vp]
+    lib.cpm_residual2.restype = ci
     lib.cpm_cp_als_workspace_bytes.argtypes = [i64p, ci, ci, ci]
     lib.cpm_cp_als_workspace_bytes.restype = sz
     lib.cpm_cp_grad_workspace_bytes.argtypes = [i64p, ci, ci, ci]
@@ -175,6 +180,30 @@ def mttkrp_all(X, dims, factors, outs=None, modes=None, dtype=None, workspace=No
                           0 if workspace is None else workspace.numel() * workspace.element_size(),
                           _stream(X.device, stream)))
     return outs
+
+
+def residual2_workspace_bytes(dims, R, dtype):
+    return load().cpm_residual2_workspace_bytes(_dims(dims), len(dims), int(R), int(dtype))
+
+
+def residual2(X, dims, factors, dtype=None, out=None, workspace=None, stream=None):
+    """||X - [[U]]||_F^2 into a float64 GPU scalar (allocated if None)."""
+    lib = load()
+    dt = _dtype_code(X, dtype)
+    _require(X, "X")
+    R = int(factors[0].shape[1])
+    for k, f in enumerate(factors):
+        _require(f, "factors[%d]" % k)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=X.device)
+    need = lib.cpm_residual2_workspace_bytes(_dims(dims), len(dims), R, dt)
+    if workspace is None:
+        workspace = _workspace(need, X.device)
+    _check(lib.cpm_residual2(X.data_ptr(), _dims(dims), len(dims), _ptrs(factors), R, dt, out.data_ptr(),
+                             None if workspace is None else workspace.data_ptr(),
+                             0 if workspace is None else workspace.numel() * workspace.element_size(),
+                             _stream(X.device, stream)))
+    return out
 
 
 def cp_als_workspace_bytes(dims, R, dtype):

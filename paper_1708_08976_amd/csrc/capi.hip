@@ -14,6 +14,7 @@
 #include "bf16_kernels.hpp"
 #include "mttkrp32_kernels.hpp"
 #include "mttkrp_kernels.hpp"
+#include "residual_kernels.hpp"
 #include "tree_kernels.hpp"
 
 using namespace cpm;
@@ -902,6 +903,111 @@ cpm_status tree_leaf(const TreePlan &t, const int64_t *dims, int N, const void *
     return tree_leaf_t<float>(t, dims, N, factors, R, n, w, (float *)out, st);
 }
 
+// ------------------------------ residual ------------------------------------
+// X viewed as Rr rows (modes s..N-1) of L contiguous entries (modes 0..s-1);
+// s maximises the used part of a work-group's 128 x 32 output tile,
+// min(Rr, 128) * min(L, 32), and among equals takes the longest rows.  K_L is split as in
+// the MTTKRP kernels: an inner group of the fastest modes (up to a 128-entry
+// chunk) and an outer scale.
+constexpr int kResChunk = 128;
+constexpr int64_t kCus = 256;            // compute units of the MI355X
+constexpr size_t kLdsPerCu = 160 * 1024; // LDS bytes per compute unit
+constexpr size_t kResStaticLds = kThreads * sizeof(double);
+// longest row of the view: 32 rows of it must stay within one buffer
+// resource's 32-bit offsets (128 L bytes below kRsrcRange)
+constexpr int64_t kResMaxL = 33554430;
+struct ResPlan {
+    int s = 0, q = 0, LC = 32, RP = 32;
+    int64_t Rr = 1, L = 1, G_in = 1, n_outer = 1, ntiles = 1, nlc = 1, S = 1, bps = 1;
+    size_t lds = 0;
+};
+
+ResPlan plan_residual(const int64_t *dims, int N, int R) {
+    ResPlan p;
+    int64_t I = 1;
+    for (int k = 0; k < N; ++k) I *= dims[k];
+    // used part of a work-group's 128 x 32 output tile; among equals the
+    // longest rows
+    int64_t best = -1, L = 1;
+    for (int s = 0; s <= N; ++s) {
+        if (s > 0) L *= dims[s - 1];
+        if (L > kResMaxL) break;
+        const int64_t eff = std::min<int64_t>(I / L, kResRows) * std::min<int64_t>(L, 32);
+        if (eff >= best) {
+            best = eff;
+            p.s = s;
+        }
+    }
+    p.L = 1;
+    for (int k = 0; k < p.s; ++k) p.L *= dims[k];
+    p.Rr = I / p.L;
+    p.q = 0;
+    p.G_in = 1;
+    while (p.q < p.s && p.G_in < kResChunk) p.G_in *= dims[p.q++];
+    p.LC = (int)std::min<int64_t>(kResChunk, ceil_div(p.G_in, 32) * 32);
+    p.nlc = ceil_div(p.G_in, p.LC);
+    p.n_outer = p.L / p.G_in;
+    p.ntiles = ceil_div(p.Rr, kResRows);
+    p.RP = R <= 32 ? 32 : (R <= 64 ? 64 : 128);
+    p.lds = p.RP == 32 ? residual_lds_bytes<32>(p.LC)
+                       : (p.RP == 64 ? residual_lds_bytes<64>(p.LC) : residual_lds_bytes<128>(p.LC));
+    // one round of resident work-groups (LDS decides how many fit a CU)
+    const int64_t per_cu = std::max<int64_t>(1, (int64_t)kLdsPerCu / (int64_t)(p.lds + kResStaticLds));
+    const int64_t groups = kCus * per_cu;
+    int64_t S = std::max<int64_t>(1, groups / (p.ntiles * p.nlc));
+    S = std::min(S, p.n_outer);
+    p.bps = ceil_div(p.n_outer, S);
+    p.S = ceil_div(p.n_outer, p.bps);
+    return p;
+}
+
+size_t residual_ws(const int64_t *dims, int N, int R) {
+    const ResPlan p = plan_residual(dims, N, R);
+    return align_up((size_t)(p.ntiles * p.nlc * p.S) * sizeof(double));
+}
+
+template <int RP, bool BF>
+cpm_status launch_residual(const ResPlan &p, const void *X, int64_t I, const Krp<float> &kr,
+                           const Krp<float> &kin, const Krp<float> &kout, int R, double *part, hipStream_t st) {
+    const void *fn = (const void *)k_residual32<RP, BF>;
+    if (p.lds > 65536) HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds));
+    const int64_t blocks = p.ntiles * p.nlc * p.S;
+    hipLaunchKernelGGL((k_residual32<RP, BF>), dim3((unsigned)blocks), dim3(kThreads), p.lds, st, X, I, p.Rr, p.L,
+                       p.G_in, p.n_outer, kr, kin, kout, R, p.LC, p.ntiles, p.nlc, p.bps, part);
+    LAUNCH_CHECK("k_residual32");
+    return CPM_OK;
+}
+
+cpm_status residual_enqueue(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                            cpm_dtype dt, double *part, double *out, hipStream_t st) {
+    const ResPlan p = plan_residual(dims, N, R);
+    int in_modes[CPM_MAX_MODES], out_modes[CPM_MAX_MODES], r_modes[CPM_MAX_MODES];
+    int nin = 0, nout = 0, nr = 0;
+    for (int k = 0; k < p.q; ++k) in_modes[nin++] = k;
+    for (int k = p.q; k < p.s; ++k) out_modes[nout++] = k;
+    for (int k = p.s; k < N; ++k) r_modes[nr++] = k;
+    const Krp<float> kin = krp_of<float>(factors, dims, in_modes, nin);
+    const Krp<float> kout = krp_of<float>(factors, dims, out_modes, nout);
+    const Krp<float> kr = krp_of<float>(factors, dims, r_modes, nr);
+    const int64_t I = p.L * p.Rr;
+    const bool bf = dt == CPM_BF16X2;
+    cpm_status s;
+    if (p.RP == 32)
+        s = bf ? launch_residual<32, true>(p, X, I, kr, kin, kout, R, part, st)
+               : launch_residual<32, false>(p, X, I, kr, kin, kout, R, part, st);
+    else if (p.RP == 64)
+        s = bf ? launch_residual<64, true>(p, X, I, kr, kin, kout, R, part, st)
+               : launch_residual<64, false>(p, X, I, kr, kin, kout, R, part, st);
+    else
+        s = bf ? launch_residual<128, true>(p, X, I, kr, kin, kout, R, part, st)
+               : launch_residual<128, false>(p, X, I, kr, kin, kout, R, part, st);
+    if (s) return s;
+    const int64_t n = p.ntiles * p.nlc * p.S;
+    hipLaunchKernelGGL(k_sum_vector, dim3(1), dim3(kThreads), 0, st, part, (int)n, out);
+    LAUNCH_CHECK("k_sum_vector");
+    return CPM_OK;
+}
+
 // ---------------------------- ALS / gradient -------------------------------
 struct SolveWs {
     int *status;
@@ -1126,6 +1232,35 @@ cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *con
         if (s) return s;
     }
     return CPM_OK;
+}
+
+size_t cpm_residual2_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {
+    int64_t total;
+    std::string saved = g_last_error;
+    if (check_dtype(dt) || dt == CPM_F64 || check_shape(dims, N, R, &total, CPM_MAX_RANK_SOLVE)) {
+        g_last_error = saved;
+        return 0;
+    }
+    return residual_ws(dims, N, R);
+}
+
+cpm_status cpm_residual2(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                         cpm_dtype dt, double *out_dev, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    int64_t total;
+    cpm_status s = check_dtype(dt);
+    if (s) return s;
+    if (dt == CPM_F64) return fail(CPM_EUNSUPPORTED, "cpm_residual2 takes float32 or split-bf16 tensors");
+    s = check_shape(dims, N, R, &total, CPM_MAX_RANK_SOLVE);
+    if (s) return s;
+    if (!X) return fail(CPM_EINVAL, "X is null");
+    if (!out_dev) return fail(CPM_EINVAL, "out_dev is null");
+    if (!factors) return fail(CPM_EINVAL, "factors is null");
+    for (int k = 0; k < N; ++k)
+        if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    const size_t need = residual_ws(dims, N, R);
+    if (!workspace || ws_bytes < need)
+        return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    return residual_enqueue(X, dims, N, factors, R, dt, (double *)workspace, out_dev, stream);
 }
 
 size_t cpm_cp_als_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {

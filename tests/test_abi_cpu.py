@@ -147,3 +147,16 @@ def test_mttkrp_all_workspace_holds_the_group_intermediates():
     assert _abi.mttkrp_all_workspace_bytes(d, 32, _abi.CPM_F32) == max(
         _abi.mttkrp_workspace_bytes(d, 32, n, _abi.CPM_F32) for n in range(4))
     assert _abi.cp_grad_workspace_bytes(d5, 32, _abi.CPM_F32) >= inter
+
+
+def test_residual2_validates_before_launch():
+    lib = _abi.load()
+    d = _dims((8, 9, 10))
+    assert lib.cpm_residual2(None, d, 3, _ptrs(3), 4, 0, FAKE, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.cpm_residual2(FAKE, d, 3, _ptrs(3), 4, 0, None, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.cpm_residual2(FAKE, d, 3, _ptrs(3, null_at=0), 4, 0, FAKE, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.cpm_residual2(FAKE, d, 3, _ptrs(3), 4, 1, FAKE, FAKE, 1 << 30, None) == _abi.CPM_EUNSUPPORTED
+    assert lib.cpm_residual2(FAKE, d, 3, _ptrs(3), 129, 0, FAKE, FAKE, 1 << 30, None) == _abi.CPM_EUNSUPPORTED
+    assert lib.cpm_residual2(FAKE, d, 3, _ptrs(3), 4, 0, FAKE, None, 0, None) == _abi.CPM_EWORKSPACE
+    assert _abi.residual2_workspace_bytes((512, 512, 512), 32, _abi.CPM_F32) > 0
+    assert _abi.residual2_workspace_bytes((512, 512, 512), 32, _abi.CPM_F64) == 0

@@ -1,0 +1,113 @@
+"""GPU parity of cpm_residual2, the squared residual ||X - [[U]]||_F^2 with
+the model recomputed on the fly, against the oracle's entry-by-entry FP64
+residual.
+
+Tolerance, from the arithmetic: each model entry is a float32 sum of R
+products of N float32 factors, so its error is at most
+(R + N + 2) 2^-24 sum_c prod_k |U_k(i_k, c)|.  The Frobenius norm of that
+majorant has a closed form, sqrt(sum of the Hadamard product of the Grams
+of |U_k|), which gives a bound db on ||delta||; the squared residual is then
+within 2 ||E|| db + db^2 of the exact value (the float64 sums add a
+negligible I 2^-53 relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import announce, make_case
+from oracle import oracle as O
+from paper_1708_08976_amd import _abi, inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    (37, 29, 41),
+    (64, 48, 80),
+    (5, 7, 3, 11, 13),
+    (16, 33, 2, 9),
+    (1, 17, 1, 19),
+    (200, 3),
+    (3, 200),
+    (1000, 1, 1),
+    (1, 1, 1000),
+    (31, 1, 257),
+    (1, 1, 1),
+    (33, 47, 3, 2),
+    (130, 130),
+    (12, 12, 12, 12, 12),
+]
+
+
+def model_bound(U, R):
+    """db = (R + N + 2) 2^-24 ||[[|U|]]||_F, the latter from the Grams."""
+    H = np.ones((R, R))
+    for u in U:
+        a = np.abs(np.asarray(u, dtype=np.float64))
+        H *= a.T @ a
+    return (R + len(U) + 2) * 2.0 ** -24 * np.sqrt(H.sum())
+
+
+def check(got, ref, U, R):
+    db = model_bound(U, R)
+    tol = 2 * np.sqrt(max(ref, 0.0)) * db + db * db + 1e-12 * ref
+    assert abs(got - ref) <= tol, (got, ref, tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("R", [1, 13, 32, 33, 64, 70, 128])
+def test_residual2_matches_oracle(dims, R, dtype):
+    announce("residual2", dtype, dims, R)
+    X, U = make_case(dims, R, seed=sum(dims) + 3 * R)
+    Ud = [u.cuda() for u in U]
+    Uh = [u.numpy() for u in U]
+    if dtype == "f32":
+        got = _abi.residual2(X.cuda(), dims, Ud).item()
+        ref = O.residual2(X.numpy().ravel(), dims, Uh)
+    else:
+        planes = inputs.split_bf16_planes(X)
+        got = _abi.residual2(planes.cuda(), dims, Ud, dtype=_abi.CPM_BF16X2).item()
+        ref = O.residual2(planes.numpy().view(np.uint16), dims, Uh, xtype=O.BF16PAIR)
+    check(got, ref, Uh, R)
+
+
+@pytest.mark.parametrize("R", [8, 32])
+def test_residual2_of_a_close_fit(R):
+    """A rank-R model plus 1e-3 noise: the residual is 1e-6 of ||X||^2, where
+    the identity form in float32 keeps about one digit; the fused residual
+    still meets the bound against the oracle."""
+    dims = (40, 36, 44)
+    X, U = inputs.noisy_low_rank(dims, R, seed_factors=51, seed_noise=52, eta=1e-3)
+    Uh = [u.numpy() for u in U]
+    got = _abi.residual2(X.cuda(), dims, [u.cuda() for u in U]).item()
+    ref = O.residual2(X.numpy().ravel(), dims, Uh)
+    x2 = float(np.sum(X.numpy().astype(np.float64) ** 2))
+    assert ref < 1e-5 * x2
+    check(got, ref, Uh, R)
+
+
+def test_residual2_bitwise_reproducible():
+    dims, R = (64, 48, 80), 32
+    X, U = make_case(dims, R, seed=61)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    a = _abi.residual2(Xd, dims, Ud)
+    b = _abi.residual2(Xd, dims, Ud)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(300)
+def test_residual2_512cube_fp32_r32():
+    """The 512^3 workload: rank-32 model with 1% noise and its true factors,
+    and the same tensor against the N(0,1) starting factors."""
+    dims, R = (512, 512, 512), 32
+    announce("residual2 512^3")
+    X, U = inputs.noisy_low_rank(dims, R, seed_factors=3, seed_noise=4, eta=0.01, device="cuda")
+    Xh = X.cpu().numpy().ravel()
+    for tag, F in [("true factors", U), ("start factors", inputs.normal_factors(dims, R, seed=5, device="cuda"))]:
+        Fh = [f.cpu().numpy() for f in F]
+        got = _abi.residual2(X, dims, F).item()
+        ref = O.residual2(Xh, dims, Fh)
+        print("512^3 residual2 (%s): gpu %.12e oracle %.12e rel %.2e" % (tag, got, ref, abs(got - ref) / ref),
+              flush=True)
+        check(got, ref, Fh, R)
