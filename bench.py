@@ -253,6 +253,31 @@ def extra_measurements(torch, _abi, inputs, X2, dims2, U2, stream):
     torch.cuda.synchronize()
     out["cp_als_20_sweeps_512cube_r32"] = {"ms": round(t0.elapsed_time(t1), 3), "final_fit": round(fit, 6)}
 
+    # Exact squared residual ||X - [[U]]||^2 of the fitted model (one pass
+    # over X, the model formed on the fly), float32 and split bf16, next to
+    # the identity form the ALS fit uses.
+    P2 = _abi.split_bf16(X2.reshape(-1))
+    r2 = torch.empty((), dtype=torch.float64, device=dev)
+    rec = {}
+    for dt, tag, Xin in [(_abi.CPM_F32, "fp32", X2), (_abi.CPM_BF16X2, "bf16x2", P2)]:
+        wsr = torch.empty(max(1, _abi.residual2_workspace_bytes(dims2, 32, dt)), dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            _abi.residual2(Xin, dims2, Ub, dtype=dt, out=r2, workspace=wsr)
+        t0 = timer.event()
+        for _ in range(reps * 4):
+            _abi.residual2(Xin, dims2, Ub, dtype=dt, out=r2, workspace=wsr)
+        t1 = timer.event()
+        torch.cuda.synchronize()
+        us = t0.elapsed_time(t1) / (reps * 4) * 1e3
+        nbytes = 4 * 512 ** 3
+        rec[tag] = {"us": round(us, 1), "GB/s": round(nbytes / us / 1e3, 1),
+                    "hbm_frac": round(nbytes / us / 1e3 / HBM_PEAK_GBS, 4),
+                    "fit_exact": round(1.0 - (r2.item() ** 0.5) / (xn ** 0.5), 9)}
+        del wsr
+    rec["fit_identity_form"] = round(fit, 9)
+    out["residual2_512cube_r32"] = rec
+    del P2
+
     # 256x256x512x32 correlation-style tensor: float32 at R=64; split bf16
     # against float32 at R=128 (same tensor, same factors).
     dims3 = (256, 256, 512, 32)

@@ -69,6 +69,13 @@ def cp_grad(X, factors, xnorm2=-1.0):
     return list(reversed(grads)), loss
 
 
+def residual2(X, factors):
+    """||X - [[U]]||_F^2 as a float64 GPU scalar, the model recomputed on the
+    fly while X streams once (float32 or split-bf16 tensors)."""
+    buf, dims, pf, dt, N = _paper(X, factors)
+    return _abi.residual2(buf, dims, pf, dtype=dt)
+
+
 def xnorm2(X):
     buf, dims, _, dt, _ = _paper(X, [None] * len(X.shape))
     return _abi.xnorm2(buf, dims, dtype=dt)
@@ -77,18 +84,23 @@ def xnorm2(X):
 class CPLoss(torch.autograd.Function):
     """f(U_0..U_{N-1}) = 1/2 ||X - [[U]]||_F^2 for a fixed tensor X.
 
-    forward: one MTTKRP (the last paper mode) and the Grams give f by
-    ||X||^2 - 2 <M, U> + sum(Hadamard of the Grams); the residual X - [[U]]
-    is never formed or stored.  backward: the hand-written gradient
-    U_n H_n - MTTKRP_n for every factor, recomputing the MTTKRPs.  X gets no
-    gradient.
+    forward: by default one MTTKRP (the last paper mode) and the Grams give
+    f by ||X||^2 - 2 <M, U> + sum(Hadamard of the Grams); with exact=True
+    the residual is recomputed entry by entry in one pass over X
+    (cpm_residual2; float32 and split-bf16 tensors), which loses nothing to
+    cancellation when the model fits closely.  Either way X - [[U]] is never
+    stored.  backward: the hand-written gradient U_n H_n - MTTKRP_n for
+    every factor, recomputing the MTTKRPs.  X gets no gradient.
     """
 
     @staticmethod
-    def forward(ctx, X, xnorm2, *factors):
+    def forward(ctx, X, xnorm2, exact, *factors):
         buf, dims, pf, dt, N = _paper(X, factors)
         xn = -1.0 if xnorm2 is None else float(xnorm2)
-        _, loss = _abi.cp_grad(buf, dims, pf, grads=False, xnorm2=xn, dtype=dt)
+        if exact:
+            loss = _abi.residual2(buf, dims, pf, dtype=dt).mul_(0.5)
+        else:
+            _, loss = _abi.cp_grad(buf, dims, pf, grads=False, xnorm2=xn, dtype=dt)
         ctx.X = X
         ctx.xnorm2 = xn
         ctx.save_for_backward(*factors)
@@ -101,8 +113,8 @@ class CPLoss(torch.autograd.Function):
         grads, _ = _abi.cp_grad(buf, dims, pf, xnorm2=ctx.xnorm2, dtype=dt)
         scale = g.to(grads[0].dtype)
         out = [gr.mul_(scale) for gr in reversed(grads)]
-        return (None, None) + tuple(out)
+        return (None, None, None) + tuple(out)
 
 
-def cp_loss(X, factors, xnorm2=None):
-    return CPLoss.apply(X, xnorm2, *factors)
+def cp_loss(X, factors, xnorm2=None, exact=False):
+    return CPLoss.apply(X, xnorm2, bool(exact), *factors)

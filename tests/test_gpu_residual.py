@@ -111,3 +111,34 @@ def test_residual2_512cube_fp32_r32():
         print("512^3 residual2 (%s): gpu %.12e oracle %.12e rel %.2e" % (tag, got, ref, abs(got - ref) / ref),
               flush=True)
         check(got, ref, Fh, R)
+
+
+def test_cploss_exact_forward_on_a_close_fit():
+    """CPLoss with exact=True: the forward is 1/2 of the fused residual, so on
+    a model that fits to 1e-3 it meets the oracle's direct loss within the
+    float32-model bound, where the identity form may not; the backward is
+    the same hand-written gradient either way."""
+    from paper_1708_08976_amd import api
+    dims, R = (40, 36, 44), 8
+    X, U = inputs.noisy_low_rank(dims, R, seed_factors=71, seed_noise=72, eta=1e-3)
+    Uh = [u.numpy() for u in U]
+    ref = 0.5 * O.residual2(X.numpy().ravel(), dims, Uh)
+    Xt = X.cuda()  # torch shape = reversed paper dims
+    Ut = [u.cuda().requires_grad_(True) for u in reversed(U)]
+    f = api.cp_loss(Xt, Ut, exact=True)
+    db = model_bound(Uh, R)
+    assert abs(f.item() - ref) <= 0.5 * (2 * np.sqrt(2 * ref) * db + db * db) + 1e-12 * ref
+    f.backward()
+    U64 = [u.astype(np.float64) for u in Uh]
+    G, _, _ = O.cp_grad(X.numpy().ravel(), dims, U64)
+    for n in range(3):
+        # scale: the two terms U_n H_n and M_n whose difference is the gradient
+        H = np.ones((R, R))
+        for k in range(3):
+            if k != n:
+                H *= U64[k].T @ U64[k]
+        scale = np.linalg.norm(U64[n] @ H) + np.linalg.norm(G[n] + U64[n] @ H)
+        g = Ut[2 - n].grad.cpu().numpy()
+        assert np.linalg.norm(g - G[n]) <= 1e-5 * scale, n
+    # the torch-order helper is the same call
+    assert api.residual2(Xt, [u.detach() for u in Ut]).item() == pytest.approx(2 * f.item(), rel=1e-15)
