@@ -306,9 +306,19 @@ def extra_measurements(torch, _abi, inputs, X2, dims2, U2, stream):
         else:
             rec["per_mode_fp32_peak_frac"] = [round(fl / (t / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4)
                                               for t in per_mode]
+        # all four modes at once with the cross-mode reuse (modes split 2 | 2)
+        wsa = torch.empty(max(1, _abi.mttkrp_all_workspace_bytes(dims3, R, dt)), dtype=torch.uint8, device=dev)
+        _abi.mttkrp_all(Xin, dims3, U3, outs=outs, dtype=dt, workspace=wsa)
+        t0 = timer.event()
+        for _ in range(3):
+            _abi.mttkrp_all(Xin, dims3, U3, outs=outs, dtype=dt, workspace=wsa)
+        t1 = timer.event()
+        torch.cuda.synchronize()
+        rec["ms_all_modes_cross_mode_reuse"] = round(t0.elapsed_time(t1) / 3, 3)
+        rec["cross_mode_reuse_speedup"] = round(step_ms / rec["ms_all_modes_cross_mode_reuse"], 3)
         runs[tag] = rec
         out["sym4d_" + tag] = rec
-        del U3, outs, ws3
+        del U3, outs, ws3, wsa
     out["sym4d_r128_split_bf16_speedup_over_fp32"] = {
         "all_modes": round(runs["fp32_r128"]["ms_all_modes"] / runs["bf16x2_r128"]["ms_all_modes"], 3),
         "per_mode": [round(a / b, 3) for a, b in zip(runs["fp32_r128"]["per_mode_us"],

@@ -271,3 +271,25 @@ def test_grad_vanishes_at_true_factors():
     for g in G:
         assert np.abs(g).max() < 1e-10
     assert abs(ld) < 1e-20
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("R", [1, 3])
+def test_residual2_matches_dense_model(dims, R):
+    """||X - [[U]]||^2 against the dense CP tensor built from Kronecker
+    products of factor columns (Section 2.1), and zero for X = [[U]]."""
+    X = _tensor(dims, 301 + R)
+    U = _factors(dims, R, 307 + R)
+    Y = brute.cp_tensor(U)
+    assert O.residual2(X, dims, U) == pytest.approx(float(np.sum((X - Y) ** 2)), rel=1e-12)
+    assert O.residual2(Y, dims, U) <= 1e-24 * max(1.0, float(np.sum(Y ** 2)))
+
+
+def test_residual2_widens_bf16_pairs_exactly():
+    dims = (4, 3, 5)
+    U = _factors(dims, 2, 311)
+    bits = np.random.default_rng(313).integers(0, 2 ** 16, size=120, dtype=np.uint16)
+    bits[(bits & 0x7F80) == 0x7F80] &= 0x3FFF  # keep every value finite
+    as32 = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    val = as32[:60] + as32[60:]
+    assert O.residual2(bits, dims, U, xtype=O.BF16PAIR) == O.residual2(val, dims, U)
