@@ -171,3 +171,51 @@ def test_als_sweep_with_reuse_matches_oracle(dtype):
     for n, (g, r) in enumerate(zip(Ud, ref)):
         assert rel_err(g.cpu().numpy(), r) <= tol, (n, rel_err(g.cpu().numpy(), r), tol)
     assert fit == pytest.approx(fit_ref, abs=1e-10 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
+def test_mttkrp_all_wide_rank(dtype):
+    """R = 200: four 64-column blocks in every leaf, and the passes at
+    their widest rank tiling; sampled rows of every mode against the oracle."""
+    dims, R = (40, 36, 44, 30), 200
+    code = CODES[dtype]
+    assert uses_reuse(dims, R, code)
+    announce("mttkrp_all wide", dtype, dims, R)
+    X, U, Xd, planes = case_tensors(dims, R, seed=201, dtype=dtype)
+    outs = _abi.mttkrp_all(Xd, dims, [u.cuda() for u in U], dtype=code)
+    torch.cuda.synchronize()
+    Xh = X.numpy().ravel() if planes is None else planes.numpy().view(np.uint16)
+    xt = None if planes is None else O.BF16PAIR
+    Uh = [u.numpy() for u in U]
+    Xa = np.abs(X.numpy().ravel())
+    Ua = [np.abs(u) for u in Uh]
+    for n in range(4):
+        rows = sorted({0, 1, dims[n] // 2, dims[n] - 1})
+        ref = O.mttkrp_rows(Xh, dims, Uh, n, rows, xtype=xt)
+        absr = O.mttkrp_rows(Xa, dims, Ua, n, rows)
+        err = rel_err_abs(outs[n].cpu().numpy()[rows], ref, absr)
+        assert err <= TOL[dtype], (n, err)
+
+
+def test_als_sweep_with_reuse_split_bf16():
+    """One sweep on the pair tensor through the reuse scheme against the
+    oracle's sweep on the pair values."""
+    dims, R = (20, 24, 22, 26), 8
+    assert uses_reuse(dims, R, _abi.CPM_BF16X2)
+    X = inputs.uniform_tensor(dims, seed=23, dtype=torch.float32)
+    planes = inputs.split_bf16_planes(X)
+    U = inputs.normal_factors(dims, R, seed=24, dtype=torch.float32)
+    Uh = [u.numpy().astype(np.float64) for u in U]
+    ref, fit_ref = O.cp_als_step(planes.numpy().view(np.uint16), dims, Uh, xtype=O.BF16PAIR)
+    kap = 1.0
+    for n in range(4):
+        H = np.ones((R, R))
+        for m in range(4):
+            if m != n:
+                H *= ref[m].T @ ref[m]
+        kap = max(kap, np.linalg.cond(H))
+    Ud = [u.cuda() for u in U]
+    fit = _abi.cp_als_step(planes.cuda(), dims, Ud, dtype=_abi.CPM_BF16X2)
+    for n, (g, r) in enumerate(zip(Ud, ref)):
+        assert rel_err(g.cpu().numpy(), r) <= 1e-4 * kap, n
+    assert fit == pytest.approx(fit_ref, abs=1e-4)
