@@ -49,7 +49,7 @@
  * Cholesky factorisation succeeded (and to return the fit when asked).
  *
  * Limits: 1 <= N <= 12, every dim >= 1, prod(dims) < 2^62, 1 <= R <= 256
- * (R <= 128 for cp_als_step and cp_grad).
+ * (R <= 128 for float64 tensors, cp_als_step, cp_grad and cpm_residual2).
  */
 #ifndef CPMTTKRP_H
 #define CPMTTKRP_H

@@ -1191,6 +1191,7 @@ cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *con
     if (s) return s;
     s = check_shape(dims, N, R, &total, CPM_MAX_RANK);
     if (s) return s;
+    if (dt == CPM_F64 && R > 128) return fail(CPM_EUNSUPPORTED, "float64 MTTKRP supports R <= 128");
     if (!X) return fail(CPM_EINVAL, "X is null");
     if (!factors) return fail(CPM_EINVAL, "factors is null");
     if (!outs) return fail(CPM_EINVAL, "outs is null");

@@ -119,6 +119,7 @@ def test_mttkrp_all_validates_before_launch():
     d = (64,) * 5
     assert call_mttkrp_all(d, X=None) == _abi.CPM_EINVAL
     assert call_mttkrp_all(d, R=257) == _abi.CPM_EUNSUPPORTED
+    assert call_mttkrp_all(d, R=129, dt=_abi.CPM_F64) == _abi.CPM_EUNSUPPORTED  # as for mttkrp
     assert call_mttkrp_all(d, dt=9) == _abi.CPM_EINVAL
     # every factor is read (each one belongs to some other mode's product)
     assert call_mttkrp_all(d, factors=_ptrs(5, null_at=3)) == _abi.CPM_EINVAL
