@@ -202,6 +202,8 @@ constexpr int kF32GroupsRight = 512;  // two (its cross-wave reduction takes 16 
 // tight: the inner contracted group grows only while it still fits one
 // chunk (at least one mode), so the contracted range is not cut into chunks
 // whose partial results are each a whole output; used for wide outputs.
+constexpr int64_t kTightChunkMax = 512;
+constexpr size_t kTightLds = 80 * 1024;
 bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *X, bool tight) {
     const int nct = (R + 31) / 32;
     const bool left = p.IL >= 32;
@@ -248,7 +250,13 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.Q = tj;
         p.MB = wj;
         const int64_t unit = 8 * (4 / wj);
-        const int64_t lcap = kF32Chunk;
+        // tight: the whole inner group in one resident chunk while the tile
+        // and scale table stay within kTightLds (up to 512 rows)
+        int64_t lcap = kF32Chunk;
+        if (tight)
+            while (lcap + unit <= kTightChunkMax &&
+                   (size_t)4 * RP * (lcap + unit + 4) + (size_t)kScaleTableBytes <= kTightLds)
+                lcap += unit;
         int q = mode + 1;
         p.G_in = 1;
         if (tight && q < N) {
@@ -792,7 +800,8 @@ struct LeafShape {
     int rc_shift, ncb;
 };
 
-LeafShape leaf_shape(const int64_t *g, int m, int t, int R) {
+// vec: the float32 form with 4 rank columns per lane (k_tree_leaf4)
+LeafShape leaf_shape(const int64_t *g, int m, int t, int R, bool vec) {
     LeafShape q{};
     q.Ll = 1;
     for (int k = 0; k < t; ++k) q.Ll *= g[k];
@@ -800,10 +809,11 @@ LeafShape leaf_shape(const int64_t *g, int m, int t, int R) {
     int64_t Lr = 1;
     for (int k = t + 1; k < m; ++k) Lr *= g[k];
     q.pairs = q.Ll * Lr;
-    const int RC = R >= 64 ? 64 : pow2_at_least(R);
+    const int lanes = vec ? R / 4 : R;  // lanes a row's columns need
+    const int RC = lanes >= 64 ? 64 : pow2_at_least(lanes);
     q.rc_shift = 0;
     while ((1 << q.rc_shift) < RC) ++q.rc_shift;
-    q.ncb = (int)ceil_div(R, RC);
+    q.ncb = (int)ceil_div(lanes, RC);
     q.xblocks = std::min(q.It, kLeafMaxRowBlocks);
     int64_t S = ceil_div(kLeafBlocks, q.xblocks * q.ncb);
     S = std::max<int64_t>(1, std::min(S, ceil_div(q.pairs, kLeafMinPairs)));
@@ -816,8 +826,11 @@ size_t leaf_partial_bytes(const int64_t *dims, int N, int R, cpm_dtype dt, const
     size_t b = 0;
     for (int n = 0; n < N; ++n) {
         const int g0 = n < t.s ? 0 : t.s, g1 = n < t.s ? t.s : N;
-        const LeafShape q = leaf_shape(dims + g0, g1 - g0, n - g0, R);
-        if (q.S > 1) b = std::max(b, (size_t)q.S * q.It * R * dtype_f_bytes(dt));
+        for (bool vec : {false, true}) {
+            if (vec && (R % 4 != 0 || dt == CPM_F64)) continue;
+            const LeafShape q = leaf_shape(dims + g0, g1 - g0, n - g0, R, vec);
+            if (q.S > 1) b = std::max(b, (size_t)q.S * q.It * R * dtype_f_bytes(dt));
+        }
     }
     return b;
 }
@@ -882,12 +895,25 @@ cpm_status tree_leaf_t(const TreePlan &t, const int64_t *dims, int N, const void
     for (int k = g0; k < g1; ++k)
         if (k != n) om[no++] = k;
     const Krp<T> kk = krp_of<T>(factors, dims, om, no);
-    const LeafShape q = leaf_shape(dims + g0, g1 - g0, n - g0, R);
     const T *Tm = reinterpret_cast<const T *>(left ? w.TL : w.TR);
+    // 16-byte rows of T and of every factor read: the 4-column form
+    bool vec = std::is_same<T, float>::value && R % 4 == 0 && (uintptr_t)Tm % 16 == 0;
+    for (int z = 0; z < no; ++z) vec = vec && (uintptr_t)factors[om[z]] % 16 == 0;
+    const LeafShape q = leaf_shape(dims + g0, g1 - g0, n - g0, R, vec);
     T *dst = q.S > 1 ? reinterpret_cast<T *>(w.leaf) : out;
-    hipLaunchKernelGGL(k_tree_leaf<T>, dim3((unsigned)q.xblocks, (unsigned)q.S, (unsigned)q.ncb), dim3(kThreads), 0,
-                       st, Tm, q.Ll, q.It, q.pairs, q.per_split, kk, R, q.rc_shift, dst);
-    LAUNCH_CHECK("k_tree_leaf");
+    const dim3 grid((unsigned)q.xblocks, (unsigned)q.S, (unsigned)q.ncb);
+    if constexpr (std::is_same<T, float>::value) {
+        if (vec) {
+            hipLaunchKernelGGL(k_tree_leaf4, grid, dim3(kThreads), 0, st, Tm, q.Ll, q.It, q.pairs, q.per_split, kk,
+                               R, q.rc_shift, dst);
+            LAUNCH_CHECK("k_tree_leaf4");
+        }
+    }
+    if (!vec) {
+        hipLaunchKernelGGL(k_tree_leaf<T>, grid, dim3(kThreads), 0, st, Tm, q.Ll, q.It, q.pairs, q.per_split, kk, R,
+                           q.rc_shift, dst);
+        LAUNCH_CHECK("k_tree_leaf");
+    }
     if (q.S > 1) {
         const Krp<T> none{};
         hipLaunchKernelGGL((k_reduce<T, T>), dim3((unsigned)ceil_div(q.It * R, 64)), dim3(kThreads), 0, st, dst,

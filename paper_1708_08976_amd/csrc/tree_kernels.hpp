@@ -119,4 +119,95 @@ __global__ __launch_bounds__(kThreads) void k_tree_leaf(const T *__restrict__ Tm
     }
 }
 
+// Float32 form of k_tree_leaf for R a multiple of 4 with 16-byte aligned
+// factors: each lane takes 4 consecutive rank columns (16-byte loads of T
+// rows and factor rows), 2^rc_shift lanes cover a row's column block of
+// 4 * 2^rc_shift columns, and 64 >> rc_shift sub-rows run side by side.
+// Same walk, batching and fixed-order float64 sums as k_tree_leaf.
+__device__ inline f32x4 krp_slow_value4(const Krp<float> &k, int R, int64_t g, int c4) {
+    f32x4 v = {1.f, 1.f, 1.f, 1.f};
+    for (int z = 1; z < k.Z; ++z)
+        v *= *reinterpret_cast<const f32x4 *>(k.U[z] + mod64(div64(g, k.stride[z]), k.J[z]) * R + c4);
+    return v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_tree_leaf4(const float *__restrict__ Tm, int64_t Ll, int64_t It,
+                                                         int64_t pairs, int64_t per_split, Krp<float> kk, int R,
+                                                         int rc_shift, float *__restrict__ out) {
+    __shared__ double red[4][kThreads];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int RC = 1 << rc_shift;
+    const int subs = 64 >> rc_shift;
+    const int sub = lane >> rc_shift;
+    const int c4 = ((int)blockIdx.z * RC + (lane & (RC - 1))) * 4;
+    const bool col_ok = c4 < R;
+    const int cc = col_ok ? c4 : 0;
+    const int64_t p0 = (int64_t)blockIdx.y * per_split;
+    const int64_t p1 = p0 + per_split < pairs ? p0 + per_split : pairs;
+    const int workers = 4 * subs;
+    const int64_t run = (p1 - p0 + workers - 1) / workers;
+    const int64_t wk = wave * subs + sub;
+    const int64_t q0 = p0 + wk * run < p1 ? p0 + wk * run : p1;
+    const int64_t q1 = q0 + run < p1 ? q0 + run : p1;
+    const int64_t J0 = kk.Z > 0 ? kk.J[0] : 1;
+    const float *U0 = kk.Z > 0 ? kk.U[0] : nullptr;
+    const f32x4 ones = {1.f, 1.f, 1.f, 1.f}, zeros = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t i = blockIdx.x; i < It; i += gridDim.x) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (q0 < q1) {
+            const int64_t a = div64(q0, Ll);
+            int64_t b = q0 - a * Ll;
+            int64_t row = b + Ll * (i + It * a);
+            int64_t d0 = kk.Z > 0 ? mod64(q0, J0) : 0;
+            f32x4 slow = krp_slow_value4(kk, R, q0, cc);
+            for (int64_t q = q0; q < q1; q += kLeafBatch) {
+                int64_t rows[kLeafBatch];
+                f32x4 ws[kLeafBatch];
+#pragma unroll
+                for (int u = 0; u < kLeafBatch; ++u) {
+                    const bool ok = q + u < q1;
+                    rows[u] = ok ? row : -1;
+                    ws[u] = ok ? (kk.Z > 0 ? slow * *reinterpret_cast<const f32x4 *>(U0 + d0 * R + cc) : ones)
+                               : zeros;
+                    if (ok) {
+                        ++row;
+                        if (++b == Ll) {
+                            b = 0;
+                            row += Ll * (It - 1);
+                        }
+                        if (++d0 == J0) {
+                            d0 = 0;
+                            if (q + u + 1 < q1) slow = krp_slow_value4(kk, R, q + u + 1, cc);
+                        }
+                    }
+                }
+                f32x4 v[kLeafBatch];
+#pragma unroll
+                for (int u = 0; u < kLeafBatch; ++u)
+                    v[u] = (col_ok && rows[u] >= 0) ? *reinterpret_cast<const f32x4 *>(Tm + rows[u] * R + c4)
+                                                    : zeros;
+#pragma unroll
+                for (int u = 0; u < kLeafBatch; ++u)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[e] += (double)v[u][e] * (double)ws[u][e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[e][tid] = acc[e];
+        __syncthreads();
+        if (tid < RC) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double s = 0.0;
+                for (int w = 0; w < 4; ++w)
+                    for (int q = 0; q < subs; ++q) s += red[e][w * 64 + q * RC + tid];
+                const int oc = c4 + e;
+                if (oc < R) out[((int64_t)blockIdx.y * It + i) * R + oc] = (float)s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace cpm

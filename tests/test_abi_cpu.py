@@ -140,6 +140,7 @@ def test_mttkrp_all_workspace_holds_the_group_intermediates():
     per_mode = max(_abi.mttkrp_workspace_bytes(d5, 32, n, _abi.CPM_F32) for n in range(5))
     assert inter + per_mode <= ws5 <= inter + per_mode + (64 << 20)
     assert _abi.mttkrp_all_workspace_bytes(d5, 32, _abi.CPM_F64) >= 2 * inter
+    # 3-way: each mode is an ordinary MTTKRP
     d3 = (512, 512, 512)
     assert _abi.mttkrp_all_workspace_bytes(d3, 32, _abi.CPM_F32) == max(
         _abi.mttkrp_workspace_bytes(d3, 32, n, _abi.CPM_F32) for n in range(3))

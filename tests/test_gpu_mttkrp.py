@@ -195,3 +195,17 @@ def test_many_blocks_per_work_group(dtype, R):
         ref = O.mttkrp(xh, dims, [u.numpy() for u in U], n, xtype=xt)
         got = _abi.mttkrp(Xd, dims, Ud, n, dtype=code).cpu().numpy()
         assert rel_err_abs(got, ref, absr[n]) <= TOL[dtype], (n, R)
+
+
+@pytest.mark.parametrize("dims", [(4096, 300), (2048, 500, 3), (8192, 96, 2)])
+@pytest.mark.parametrize("R", [8, 32, 64])
+def test_wide_output_long_resident_chunk(dims, R):
+    """Mode 0 with a wide output and one long contracted mode: split-K
+    partials would rival X, so the float32 plan keeps the whole inner mode
+    (up to 512 rows) as one resident chunk and writes the result directly."""
+    announce("wide output", dims, R)
+    X, U = make_case(dims, R, seed=R + len(dims))
+    ref = O.mttkrp(X.numpy().ravel(), dims, [u.numpy() for u in U], 0)
+    absr = O.mttkrp(np.abs(X.numpy().ravel()), dims, [np.abs(u.numpy()) for u in U], 0)
+    got = _abi.mttkrp(X.cuda(), dims, [u.cuda() for u in U], 0).cpu().numpy()
+    assert rel_err_abs(got, ref, absr) <= TOL["f32"]
