@@ -142,3 +142,38 @@ def test_cploss_exact_forward_on_a_close_fit():
         assert np.linalg.norm(g - G[n]) <= 1e-5 * scale, n
     # the torch-order helper is the same call
     assert api.residual2(Xt, [u.detach() for u in Ut]).item() == pytest.approx(2 * f.item(), rel=1e-15)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
+def test_residual2_64p5_full_size(dtype):
+    """The 64^5 workload (rank-32 model, 5% noise) with its true factors:
+    every one of the 1.07e9 entries, against the oracle's direct residual."""
+    dims, R = (64,) * 5, 32
+    announce("residual2 64^5", dtype)
+    X, U = inputs.noisy_low_rank(dims, R, seed_factors=9, seed_noise=10, eta=0.05, device="cuda")
+    Uh = [u.cpu().numpy() for u in U]
+    if dtype == "f32":
+        got = _abi.residual2(X, dims, U).item()
+        ref = O.residual2(X.cpu().numpy().ravel(), dims, Uh)
+    else:
+        P = _abi.split_bf16(X.reshape(-1))
+        got = _abi.residual2(P, dims, U, dtype=_abi.CPM_BF16X2).item()
+        ref = O.residual2(P.cpu().numpy().view(np.uint16), dims, Uh, xtype=O.BF16PAIR)
+    print("64^5 residual2 %s: gpu %.12e oracle %.12e rel %.2e" % (dtype, got, ref, abs(got - ref) / ref), flush=True)
+    check(got, ref, Uh, R)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(300)
+def test_residual2_sym4d_fp32_r64_full_size():
+    dims, R = (256, 256, 512, 32), 64
+    announce("residual2 sym4d")
+    X = inputs.symmetric_pair_tensor(dims, seed=6, device="cuda")
+    U = inputs.normal_factors(dims, R, seed=7, device="cuda")
+    Uh = [u.cpu().numpy() for u in U]
+    got = _abi.residual2(X, dims, U).item()
+    ref = O.residual2(X.cpu().numpy().ravel(), dims, Uh)
+    print("sym4d residual2: gpu %.12e oracle %.12e rel %.2e" % (got, ref, abs(got - ref) / ref), flush=True)
+    check(got, ref, Uh, R)
