@@ -384,6 +384,24 @@ def extra_measurements(torch, _abi, inputs, X2, dims2, U2, stream):
                 "cross_mode_reuse_speedup": round(t_mode["per_mode"] / t_mode["reuse"], 3)}
             del ws5, wsa, wsm, outs5
         out["cp_grad_64p5_r%d_split_bf16_speedup_over_fp32" % R5] = round(res["fp32"] / res["bf16x2"], 3)
+        if R5 == 32:
+            # one CP-ALS sweep on 64^5 (Gauss-Seidel over the five modes with
+            # the cross-mode reuse: two passes over X instead of five)
+            Ua = [u.clone() for u in U5]
+            wsa = torch.empty(_abi.cp_als_workspace_bytes(dims5, R5, _abi.CPM_F32), dtype=torch.uint8, device=dev)
+            for _ in range(2):
+                _abi.cp_als_step(X5, dims5, Ua, xnorm2=x5, want_fit=True, workspace=wsa)
+            t0 = timer.event()
+            for _ in range(3):
+                fit5 = _abi.cp_als_step(X5, dims5, Ua, xnorm2=x5, want_fit=True, workspace=wsa)
+            t1 = timer.event()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / 3
+            one_pass = out["cp_grad_64p5_r32_fp32"]["five_mttkrps_ms_one_pass_per_mode"]
+            out["cp_als_sweep_64p5_r32"] = {"ms": round(ms, 3), "fit": round(fit5, 6),
+                                            "five_mttkrps_ms_one_pass_per_mode": one_pass,
+                                            "sweep_vs_five_single_mode_mttkrps": round(one_pass / ms, 3)}
+            del Ua, wsa
         del U5, grads
     del X5, P5
     torch.cuda.empty_cache()
