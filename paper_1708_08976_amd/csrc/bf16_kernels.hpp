@@ -331,11 +331,16 @@ __global__ __launch_bounds__(kThreads) void k_contract_right_bf16(
         }
     };
     // Transposed write: the two rows of this thread are adjacent in r, so each
-    // j gets one 32-bit (2 x bf16) store.
+    // j gets one 32-bit (2 x bf16) store.  Within a j row the four 8-entry r
+    // chunks are XOR-swizzled by (j / 8) % 4: the eight threads that differ
+    // only in jg would otherwise store to one bank (8 jg rows of 20 words
+    // are a multiple of 32 words apart).  The reads below undo the swizzle;
+    // a 16-byte A read stays one contiguous chunk.
+    const int rsw = 8 * ((rp >> 2) ^ (jg & 3)) + 2 * (rp & 3);
     auto write_tile = [&](const f32x4 (&a)[2], int buf) {
         const u16x8 v0 = __builtin_bit_cast(u16x8, a[0]);
         const u16x8 v1 = __builtin_bit_cast(u16x8, a[1]);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(xt + ((buf * 2 + plane) * JT + 8 * jg) * XP + 2 * rp);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(xt + ((buf * 2 + plane) * JT + 8 * jg) * XP + rsw);
 #pragma unroll
         for (int e = 0; e < 8; ++e) dst[e * XP / 2] = (uint32_t)v0[e] | ((uint32_t)v1[e] << 16);
     };
@@ -367,8 +372,9 @@ __global__ __launch_bounds__(kThreads) void k_contract_right_bf16(
 #pragma unroll
         for (int a = 0; a < MBW; ++a) {
             const int j = 16 * (wm * MBW + a) + m;
-            const bf16x8 ah = as_bf16x8(*reinterpret_cast<const f32x4 *>(xb + j * XP + 8 * kg));
-            const bf16x8 al = as_bf16x8(*reinterpret_cast<const f32x4 *>(xb + JT * XP + j * XP + 8 * kg));
+            const int ch = kg ^ ((j >> 3) & 3);  // swizzled position of r chunk kg in row j
+            const bf16x8 ah = as_bf16x8(*reinterpret_cast<const f32x4 *>(xb + j * XP + 8 * ch));
+            const bf16x8 al = as_bf16x8(*reinterpret_cast<const f32x4 *>(xb + JT * XP + j * XP + 8 * ch));
 #pragma unroll
             for (int b = 0; b < NBW; ++b) {
                 const int c = 16 * (wn * NBW + b) + m;
