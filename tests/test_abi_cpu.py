@@ -162,3 +162,12 @@ def test_residual2_validates_before_launch():
     assert lib.cpm_residual2(FAKE, d, 3, _ptrs(3), 4, 0, FAKE, None, 0, None) == _abi.CPM_EWORKSPACE
     assert _abi.residual2_workspace_bytes((512, 512, 512), 32, _abi.CPM_F32) > 0
     assert _abi.residual2_workspace_bytes((512, 512, 512), 32, _abi.CPM_F64) == 0
+
+
+def test_mttkrp_all_with_no_requested_mode_is_a_no_op():
+    """Every output pointer null: validation passes and nothing is launched
+    (so this runs without a GPU)."""
+    d = (64,) * 5
+    need = _abi.mttkrp_all_workspace_bytes(d, 32, _abi.CPM_F32)
+    nulls = (ctypes.c_void_p * 5)(*([None] * 5))
+    assert call_mttkrp_all(d, R=32, outs=nulls, ws=FAKE, ws_len=need) == _abi.CPM_OK
