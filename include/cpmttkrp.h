@@ -48,8 +48,13 @@
  * except cp_als_step, which waits once for the stream to learn whether every
  * Cholesky factorisation succeeded (and to return the fit when asked).
  *
- * Limits: 1 <= N <= 12, every dim >= 1, prod(dims) < 2^62, 1 <= R <= 256
- * (R <= 128 for float64 tensors, cp_als_step, cp_grad and cpm_residual2).
+ * Limits: 2 <= N <= 12 (N outside gives CPM_EINVAL), every dim >= 1,
+ * prod(dims) < 2^62, 1 <= R <= 256 (R <= 128 for cp_als_step, whose
+ * float64 Cholesky factorisation keeps the R x R matrix in one work-group's
+ * LDS, and for cpm_residual2).  Every factor that a call reads must span
+ * fewer than 2^32 - 256 bytes (I_k * R * element size), the reach of one
+ * buffer resource; larger factors give CPM_EUNSUPPORTED.  Larger R gives
+ * CPM_EUNSUPPORTED.
  */
 #ifndef CPMTTKRP_H
 #define CPMTTKRP_H
@@ -102,6 +107,19 @@ size_t cpm_mttkrp_workspace_bytes(const int64_t *dims, int N, int R, int mode, c
 cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
                   int mode, void *out, cpm_dtype dt, void *workspace, size_t ws_bytes,
                   hipStream_t stream);
+
+/*
+ * Diagnostics: writes into buf (at most len bytes, NUL-terminated) the
+ * kernel and launch shape `mttkrp` would use for this shape, mode, rank and
+ * type -- the contraction kernel with its template parameters, its grid,
+ * LDS bytes, Khatri-Rao chunk, inner/outer split (Section 4.1's reuse at
+ * tile level), split-K count and whether the fixed-order reduction runs.
+ * X is used only for its address alignment (never dereferenced; null means
+ * 16-byte aligned is not assumed).  Host only, launches nothing.  Returns
+ * a cpm_status (CPM_EINVAL for bad arguments or an empty buffer).
+ */
+int cpm_mttkrp_describe(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const void *X, char *buf,
+                        size_t len);
 
 /*
  * Bytes of workspace `mttkrp_all` needs (0 for invalid arguments).
@@ -185,7 +203,7 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
  * xnorm2: ||X||_F^2 if known, negative to compute it on the device.
  * The MTTKRPs are formed as by `mttkrp_all` (two passes over X from N = 4
  * on when three or more modes are wanted).
- * R <= 128.
+ * R <= 256: the gradient needs no factorisation.
  */
 cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
                    void *const *grads, double xnorm2, double *loss_dev, cpm_dtype dt,

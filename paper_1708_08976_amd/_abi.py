@@ -17,7 +17,7 @@ CPM_F32, CPM_F64, CPM_BF16X2 = 0, 1, 2
 STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_EUNSUPPORTED", 3: "CPM_ENOTPD",
                 4: "CPM_EHIP", 5: "CPM_EWORKSPACE"}
 
-EXPORTS = ["cpm_version", "cpm_last_error", "cpm_mttkrp_workspace_bytes", "mttkrp",
+EXPORTS = ["cpm_version", "cpm_last_error", "cpm_mttkrp_workspace_bytes", "mttkrp", "cpm_mttkrp_describe",
            "cpm_mttkrp_all_workspace_bytes", "mttkrp_all",
            "cpm_residual2_workspace_bytes", "cpm_residual2",
            "cpm_cp_als_workspace_bytes", "cpm_cp_grad_workspace_bytes", "cp_als_step", "cp_grad",
@@ -51,6 +51,8 @@ def load():
     lib.cpm_mttkrp_workspace_bytes.restype = sz
     lib.mttkrp.argtypes = [vp, i64p, ci, vpp, ci, ci, vp, ci, vp, sz, vp]
     lib.mttkrp.restype = ci
+    lib.cpm_mttkrp_describe.argtypes = [i64p, ci, ci, ci, ci, vp, ctypes.c_char_p, sz]
+    lib.cpm_mttkrp_describe.restype = ci
     lib.cpm_mttkrp_all_workspace_bytes.argtypes = [i64p, ci, ci, ci]
     lib.cpm_mttkrp_all_workspace_bytes.restype = sz
     lib.mttkrp_all.argtypes = [vp, i64p, ci, vpp, ci, vpp, ci, vp, sz, vp]
@@ -149,6 +151,16 @@ def mttkrp(X, dims, factors, mode, out=None, dtype=None, workspace=None, stream=
     _check(lib.mttkrp(X.data_ptr(), _dims(dims), len(dims), _ptrs(factors), R, int(mode), out.data_ptr(), dt,
                       ws_ptr, ws_len, _stream(X.device, stream)))
     return out
+
+
+def describe(dims, R, mode, dtype, X=None):
+    """Kernel and launch shape mttkrp picks (X only for its alignment: a
+    tensor, an integer address, or None for a 4096-byte aligned one)."""
+    lib = load()
+    addr = 4096 if X is None else (X if isinstance(X, int) else X.data_ptr())
+    buf = ctypes.create_string_buffer(512)
+    _check(lib.cpm_mttkrp_describe(_dims(dims), len(dims), int(R), int(mode), int(dtype), addr, buf, 512))
+    return buf.value.decode()
 
 
 def mttkrp_all_workspace_bytes(dims, R, dtype):

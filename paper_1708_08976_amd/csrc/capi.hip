@@ -57,7 +57,7 @@ size_t dtype_f_bytes(cpm_dtype dt) { return dt == CPM_F64 ? 8 : 4; }
 // Shape checks shared by every tensor entry point.  Touches host memory only.
 cpm_status check_shape(const int64_t *dims, int N, int R, int64_t *total, int Rmax) {
     if (!dims) return fail(CPM_EINVAL, "dims is null");
-    if (N < 1 || N > CPM_MAX_MODES) return fail(CPM_EINVAL, "N=%d outside [1, %d]", N, CPM_MAX_MODES);
+    if (N < 2 || N > CPM_MAX_MODES) return fail(CPM_EINVAL, "N=%d outside [2, %d]", N, CPM_MAX_MODES);
     if (R < 1) return fail(CPM_EINVAL, "R=%d < 1", R);
     if (R > Rmax) return fail(CPM_EUNSUPPORTED, "R=%d above the limit %d", R, Rmax);
     int64_t t = 1;
@@ -72,6 +72,19 @@ cpm_status check_shape(const int64_t *dims, int N, int R, int64_t *total, int Rm
 
 cpm_status check_dtype(cpm_dtype dt) {
     if (dt != CPM_F32 && dt != CPM_F64 && dt != CPM_BF16X2) return fail(CPM_EINVAL, "unknown dtype %d", (int)dt);
+    return CPM_OK;
+}
+
+constexpr int64_t kMaxBufferOffset = 0xFFFFFF00LL;  // reach of one buffer resource
+
+// Factor rows are read through buffer resources whose range is 32 bits:
+// every factor read (all but `skip`, -1 for none) must span less than
+// kMaxBufferOffset bytes.
+cpm_status check_factor_reach(const int64_t *dims, int N, int R, cpm_dtype dt, int skip) {
+    for (int k = 0; k < N; ++k)
+        if (k != skip && dims[k] * (int64_t)R * (int64_t)dtype_f_bytes(dt) >= kMaxBufferOffset)
+            return fail(CPM_EUNSUPPORTED, "factor %d (%lld x %d) spans 4 GiB or more, beyond one buffer resource",
+                        k, (long long)dims[k], R);
     return CPM_OK;
 }
 
@@ -103,7 +116,6 @@ struct Plan {
 
 constexpr int kTargetGroups = 512;        // about two resident work-groups per CU
 constexpr size_t kTileBytes = 78 * 1024;   // LDS for the resident Khatri-Rao tile
-constexpr int64_t kMaxBufferOffset = 0xFFFFFF00LL;  // reach of one buffer resource
 
 int pow2_at_least(int v) {
     int p = 1;
@@ -706,14 +718,13 @@ cpm_status validate_mttkrp(const void *X, const int64_t *dims, int N, const void
     if (s) return s;
     s = check_shape(dims, N, R, total, CPM_MAX_RANK);
     if (s) return s;
-    if (dt == CPM_F64 && R > 128) return fail(CPM_EUNSUPPORTED, "float64 MTTKRP supports R <= 128");
     if (!X) return fail(CPM_EINVAL, "X is null");
     if (!out) return fail(CPM_EINVAL, "out is null");
     if (!factors) return fail(CPM_EINVAL, "factors is null");
     if (mode < 0 || mode >= N) return fail(CPM_EINVAL, "mode=%d outside [0, %d)", mode, N);
     for (int k = 0; k < N; ++k)
         if (k != mode && !factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
-    return CPM_OK;
+    return check_factor_reach(dims, N, R, dt, mode);
 }
 
 size_t mttkrp_ws(const int64_t *dims, int N, int R, int mode, cpm_dtype dt) {
@@ -1200,6 +1211,41 @@ cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *
     return run_mttkrp(p, X, dims, N, factors, R, mode, out, dt, workspace, stream);
 }
 
+int cpm_mttkrp_describe(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const void *X, char *buf,
+                        size_t len) {
+    int64_t total;
+    cpm_status s = check_dtype(dt);
+    if (s) return s;
+    s = check_shape(dims, N, R, &total, CPM_MAX_RANK);
+    if (s) return s;
+    if (mode < 0 || mode >= N) return fail(CPM_EINVAL, "mode=%d outside [0, %d)", mode, N);
+    if (!buf || len == 0) return fail(CPM_EINVAL, "buf is null or empty");
+    const Plan p = make_plan(dims, N, R, mode, dt, X);
+    char name[96];
+    switch (p.kind) {
+    case kLeft32: snprintf(name, sizeof(name), "k_left32<NC=%d,WM=%d>", p.NB, p.MB); break;
+    case kRight32: snprintf(name, sizeof(name), "k_right32<NC=%d,TJ=%d,WJ=1>", p.NB, p.Q); break;
+    case kLeft:
+        snprintf(name, sizeof(name), "k_contract_left<%s,NB=%d,MB=%d,V4=%d,Q=%d>", dt == CPM_F64 ? "f64" : "f32",
+                 p.NB, p.MB, (int)p.v4, p.Q);
+        break;
+    case kRight:
+        snprintf(name, sizeof(name), "k_contract_right<%s,NB=%d,MJ=1,V4=%d>", dt == CPM_F64 ? "f64" : "f32",
+                 p.NB, (int)p.v4);
+        break;
+    case kBf16Left:
+        snprintf(name, sizeof(name), "k_contract_left_bf16<NB=%d,MB=%d,Q=%d,V8=%d,WM=%d>", p.NB, p.MB, p.Q,
+                 (int)p.v4, p.WMg);
+        break;
+    default: snprintf(name, sizeof(name), "k_contract_right_bf16<NB=%d,V8=%d>", p.NB, (int)p.v4); break;
+    }
+    snprintf(buf, len, "%s grid=(%lld,%lld,%d) lds=%zu chunk=%d steps_per_block=%d inner=%lld outer_blocks=%lld "
+             "splits=%lld chunks=%lld reduce=%d",
+             name, (long long)p.ntiles, (long long)(p.S * p.nlc), p.ncb, p.lds, p.LC, p.SPB, (long long)p.G_in,
+             (long long)p.n_outer, (long long)p.S, (long long)p.nlc, (int)p.reduce);
+    return CPM_OK;
+}
+
 size_t cpm_mttkrp_all_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {
     int64_t total;
     std::string saved = g_last_error;
@@ -1217,12 +1263,13 @@ cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *con
     if (s) return s;
     s = check_shape(dims, N, R, &total, CPM_MAX_RANK);
     if (s) return s;
-    if (dt == CPM_F64 && R > 128) return fail(CPM_EUNSUPPORTED, "float64 MTTKRP supports R <= 128");
     if (!X) return fail(CPM_EINVAL, "X is null");
     if (!factors) return fail(CPM_EINVAL, "factors is null");
     if (!outs) return fail(CPM_EINVAL, "outs is null");
     for (int k = 0; k < N; ++k)
         if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    s = check_factor_reach(dims, N, R, dt, -1);
+    if (s) return s;
     const size_t need = layout_all(dims, N, R, dt, nullptr, 0).need;
     if (need > 0 && (!workspace || ws_bytes < need))
         return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
@@ -1284,6 +1331,8 @@ cpm_status cpm_residual2(const void *X, const int64_t *dims, int N, const void *
     if (!factors) return fail(CPM_EINVAL, "factors is null");
     for (int k = 0; k < N; ++k)
         if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    s = check_factor_reach(dims, N, R, dt, -1);
+    if (s) return s;
     const size_t need = residual_ws(dims, N, R);
     if (!workspace || ws_bytes < need)
         return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
@@ -1303,7 +1352,7 @@ size_t cpm_cp_als_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype d
 size_t cpm_cp_grad_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {
     int64_t total;
     std::string saved = g_last_error;
-    if (check_dtype(dt) || check_shape(dims, N, R, &total, CPM_MAX_RANK_SOLVE)) {
+    if (check_dtype(dt) || check_shape(dims, N, R, &total, CPM_MAX_RANK)) {
         g_last_error = saved;
         return 0;
     }
@@ -1321,6 +1370,8 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
     if (!factors) return fail(CPM_EINVAL, "factors is null");
     for (int k = 0; k < N; ++k)
         if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    s = check_factor_reach(dims, N, R, dt, -1);
+    if (s) return s;
     const size_t need = layout_solve(dims, N, R, dt, nullptr, true).need;
     if (!workspace || ws_bytes < need)
         return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
@@ -1435,12 +1486,14 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
     int64_t total;
     cpm_status s = check_dtype(dt);
     if (s) return s;
-    s = check_shape(dims, N, R, &total, CPM_MAX_RANK_SOLVE);
+    s = check_shape(dims, N, R, &total, CPM_MAX_RANK);
     if (s) return s;
     if (!X) return fail(CPM_EINVAL, "X is null");
     if (!factors) return fail(CPM_EINVAL, "factors is null");
     for (int k = 0; k < N; ++k)
         if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    s = check_factor_reach(dims, N, R, dt, -1);
+    if (s) return s;
     const size_t need = layout_solve(dims, N, R, dt, nullptr, false).need;
     if (!workspace || ws_bytes < need)
         return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);

@@ -20,12 +20,21 @@ def rel_err(got, ref):
 
 
 def rel_err_abs(got, ref, ref_abs):
-    """Normwise error scaled by the MTTKRP of |X| and |U_k|: the size of the
-    terms being summed, which bounds rounding error whatever the
-    cancellation in the sum (a result that happens to be tiny still has
-    errors of the order of its largest terms)."""
+    """Error scaled by the MTTKRP of |X| and |U_k| (the size of the summed
+    terms) instead of by the result.  Used only for the named cases whose
+    result is cancellation-small, where no float32 summation can meet a
+    relative bound on the result itself (see CANCELLATION_CASES)."""
     got = np.asarray(got, dtype=np.float64)
     return np.linalg.norm(got - ref) / max(np.linalg.norm(ref_abs), 1e-300)
+
+
+# (dims, R, mode) of sweep cases whose result is dominated by cancellation:
+# the summed terms are over 1e3 times the result (checked where used).
+# (1, 1, 1000) at R = 1, mode 0: one output value, the sum of 1000 terms of
+# total size 298 that comes to -0.0108 (a factor 2.8e4); a sequential
+# float32 sum is off by 9e-4 relative.
+CANCELLATION_CASES = {((1, 1, 1000), 1, 0)}
+CANCELLATION_MIN_RATIO = 1e3
 
 
 def make_case(dims, R, seed, dtype=torch.float32):
@@ -37,12 +46,6 @@ def make_case(dims, R, seed, dtype=torch.float32):
 def oracle_all_modes(X, dims, U):
     Xh = X.numpy().ravel()
     Uh = [u.numpy() for u in U]
-    return [O.mttkrp(Xh, dims, Uh, n) for n in range(len(dims))]
-
-
-def oracle_abs_all_modes(X, dims, U):
-    Xh = np.abs(X.numpy().ravel())
-    Uh = [np.abs(u.numpy()) for u in U]
     return [O.mttkrp(Xh, dims, Uh, n) for n in range(len(dims))]
 
 

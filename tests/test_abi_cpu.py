@@ -63,11 +63,22 @@ def call_mttkrp(dims, R=8, mode=0, X=FAKE, out=FAKE, dt=0, factors=None, ws=None
     (dict(dims=(4, 5, 6), X=None), _abi.CPM_EINVAL),
     (dict(dims=(4, 5, 6), out=None), _abi.CPM_EINVAL),
     (dict(dims=(4, 5, 6), dt=7), _abi.CPM_EINVAL),
-    (dict(dims=(4, 5, 6), dt=1, R=129), _abi.CPM_EUNSUPPORTED),
+    (dict(dims=(4, 5, 6), dt=1, R=257), _abi.CPM_EUNSUPPORTED),
+    (dict(dims=(4,), N=1), _abi.CPM_EINVAL),
+    # factor 0 spans 2^24 * 64 * 4 bytes = 4 GiB: beyond one buffer resource
+    (dict(dims=(1 << 24, 4, 4), R=64, mode=1), _abi.CPM_EUNSUPPORTED),
+    (dict(dims=(1 << 23, 4, 4), R=64, mode=1, dt=1), _abi.CPM_EUNSUPPORTED),
 ])
 def test_mttkrp_rejects_bad_arguments(case, expect):
     assert call_mttkrp(**case) == expect
     assert _abi.last_error() != ""
+
+
+def test_factor_reach_names_the_factor():
+    assert call_mttkrp((1 << 24, 4, 4), R=64, mode=1) == _abi.CPM_EUNSUPPORTED
+    assert "factor 0" in _abi.last_error()
+    assert call_mttkrp((4, 1 << 24, 4), R=64, mode=0) == _abi.CPM_EUNSUPPORTED
+    assert "factor 1" in _abi.last_error()
 
 
 def test_mttkrp_rejects_null_factor_except_own_mode():
@@ -89,6 +100,10 @@ def test_workspace_queries():
     assert _abi.cp_als_workspace_bytes((60, 50, 40), 8, _abi.CPM_F64) > 0
     assert _abi.cp_grad_workspace_bytes((64,) * 5, 32, _abi.CPM_F32) > 0
     assert _abi.cp_als_workspace_bytes((60, 50, 40), 129, _abi.CPM_F32) == 0
+    # the gradient needs no factorisation: R up to 256
+    assert _abi.cp_grad_workspace_bytes((60, 50, 40), 256, _abi.CPM_F32) > 0
+    assert _abi.cp_grad_workspace_bytes((60, 50, 40), 257, _abi.CPM_F32) == 0
+    assert _abi.mttkrp_workspace_bytes((60, 50, 40), 256, 1, _abi.CPM_F64) > 0
 
 
 def test_solver_entry_points_validate():
@@ -104,6 +119,31 @@ def test_solver_entry_points_validate():
     assert lib.cpm_krp_rows(_ptrs(2), _dims((3, 4)), 2, 5, 10, 5, FAKE, 0, None) == _abi.CPM_EINVAL
     assert lib.cpm_krp_rows(_ptrs(2), _dims((3, 4)), 0, 5, 0, 5, FAKE, 0, None) == _abi.CPM_EINVAL
     assert lib.cpm_xnorm2(FAKE, d, 3, 0, FAKE, None, 0, None) == _abi.CPM_EWORKSPACE
+    # cp_grad: R = 256 passes validation (stops at the workspace), 257 does not
+    assert lib.cp_grad(FAKE, d, 3, _ptrs(3), 256, None, -1.0, None, 0, None, 0, None) == _abi.CPM_EWORKSPACE
+    assert lib.cp_grad(FAKE, d, 3, _ptrs(3), 257, None, -1.0, None, 0, FAKE, 1 << 30, None) == _abi.CPM_EUNSUPPORTED
+    assert lib.cp_grad(FAKE, d, 1, _ptrs(1), 8, None, -1.0, None, 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.cp_als_step(FAKE, d, 1, _ptrs(1), 8, 0, -1.0, None, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    big = _dims((1 << 24, 4, 4))
+    assert lib.cp_grad(FAKE, big, 3, _ptrs(3), 64, None, -1.0, None, 0, FAKE, 1 << 40, None) == _abi.CPM_EUNSUPPORTED
+    assert lib.cp_als_step(FAKE, big, 3, _ptrs(3), 64, 0, -1.0, None, FAKE, 1 << 40, None) == _abi.CPM_EUNSUPPORTED
+    assert lib.cpm_residual2(FAKE, big, 3, _ptrs(3), 64, 0, FAKE, FAKE, 1 << 40, None) == _abi.CPM_EUNSUPPORTED
+
+
+def test_describe_names_the_kernel_and_launch():
+    d = _abi.describe((512, 512, 512), 32, 1, _abi.CPM_F32)
+    assert d.startswith("k_left32<NC=1,WM=1>") and "grid=" in d
+    assert _abi.describe((512, 512, 512), 32, 0, _abi.CPM_F32).startswith("k_right32<")
+    assert _abi.describe((60, 50, 40), 8, 0, _abi.CPM_F64).startswith("k_contract_right<f64")
+    assert _abi.describe((256, 256, 512, 32), 128, 0, _abi.CPM_BF16X2).startswith("k_contract_right_bf16<NB=8")
+    # rows not 16-byte aligned: the 16x16 float kernels
+    assert _abi.describe((60, 50, 40), 8, 1, _abi.CPM_F32, X=4100).startswith("k_contract_left<f32")
+    lib = _abi.load()
+    buf = ctypes.create_string_buffer(8)
+    assert lib.cpm_mttkrp_describe(_dims((4, 5, 6)), 3, 8, 3, 0, 4096, buf, 8) == _abi.CPM_EINVAL
+    assert lib.cpm_mttkrp_describe(_dims((4, 5, 6)), 3, 8, 0, 0, 4096, None, 0) == _abi.CPM_EINVAL
+    assert lib.cpm_mttkrp_describe(_dims((4, 5, 6)), 3, 8, 0, 0, 4096, buf, 8) == _abi.CPM_OK
+    assert len(buf.value) == 7  # truncated, NUL-terminated
 
 
 def call_mttkrp_all(dims, R=8, X=FAKE, dt=0, factors=None, outs=None, ws=None, ws_len=0):
@@ -119,7 +159,8 @@ def test_mttkrp_all_validates_before_launch():
     d = (64,) * 5
     assert call_mttkrp_all(d, X=None) == _abi.CPM_EINVAL
     assert call_mttkrp_all(d, R=257) == _abi.CPM_EUNSUPPORTED
-    assert call_mttkrp_all(d, R=129, dt=_abi.CPM_F64) == _abi.CPM_EUNSUPPORTED  # as for mttkrp
+    assert call_mttkrp_all(d, R=257, dt=_abi.CPM_F64) == _abi.CPM_EUNSUPPORTED  # as for mttkrp
+    assert call_mttkrp_all((1 << 24, 4, 4, 2), R=64) == _abi.CPM_EUNSUPPORTED  # factor 0 beyond 4 GiB
     assert call_mttkrp_all(d, dt=9) == _abi.CPM_EINVAL
     # every factor is read (each one belongs to some other mode's product)
     assert call_mttkrp_all(d, factors=_ptrs(5, null_at=3)) == _abi.CPM_EINVAL

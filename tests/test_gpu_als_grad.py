@@ -77,6 +77,45 @@ def test_als_not_positive_definite_restores_factors(dtype):
         assert torch.equal(b, u)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("dims,R", [((130, 140, 150), 96), ((130, 140, 150), 128), ((24, 20, 18, 16), 96),
+                                    ((24, 20, 18, 16), 128)])
+def test_als_sweep_wide_rank(dtype, dims, R):
+    """R above 64: the Cholesky factorisation keeps up to 128 KB of H in LDS
+    and the row solves read L from memory with two entries per lane; one
+    sweep against the oracle's sweep."""
+    announce("als wide", dims, R, dtype)
+    X = inputs.uniform_tensor(dims, seed=R + 1, dtype=dtype)
+    U = inputs.normal_factors(dims, R, seed=R + 2, dtype=dtype)
+    Uh = [u.numpy().astype(np.float64) for u in U]
+    ref, fit_ref = O.cp_als_step(X.numpy().ravel(), dims, Uh)
+    kap = kappa_max(dims, ref)
+    Ud = [u.cuda() for u in U]
+    fit = _abi.cp_als_step(X.cuda(), dims, Ud)
+    tol = 1e-5 * kap if dtype == torch.float32 else max(1e-10, 1e-14 * kap)
+    for n, (g, r) in enumerate(zip(Ud, ref)):
+        e = rel_err(g.cpu().numpy(), r)
+        print("als R=%d mode %d: relative error %.3e (kappa %.2e)" % (R, n, e, kap), flush=True)
+        assert e <= tol, (n, e, tol)
+    assert fit == pytest.approx(fit_ref, abs=1e-5 if dtype == torch.float32 else 1e-10)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_als_not_positive_definite_restores_factors_r128(dtype):
+    """The 128 KB-LDS factorisation detects the zero pivot too, and every
+    factor comes back unchanged."""
+    dims, R = (40, 36, 30), 128
+    X = inputs.normal_tensor(dims, seed=43, dtype=dtype).cuda()
+    U = [u.cuda() for u in inputs.normal_factors(dims, R, seed=44, dtype=dtype)]
+    U[2][:, 1] = 0.0
+    before = [u.clone() for u in U]
+    with pytest.raises(_abi.CpmError) as e:
+        _abi.cp_als_step(X, dims, U)
+    assert e.value.status == _abi.CPM_ENOTPD
+    for b, u in zip(before, U):
+        assert torch.equal(b, u)
+
+
 def test_als_twenty_iterations_fit_tracks_oracle():
     """Short run of ALS on a noisy low-rank tensor: the fit after each sweep
     agrees with the oracle's (iterates diverge slowly by rounding, so the
@@ -96,7 +135,8 @@ def test_als_twenty_iterations_fit_tracks_oracle():
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-@pytest.mark.parametrize("dims,R", [((20, 24, 28), 8), ((9, 10, 11, 12), 20), ((12, 12, 12, 12, 12), 32)])
+@pytest.mark.parametrize("dims,R", [((20, 24, 28), 8), ((9, 10, 11, 12), 20), ((12, 12, 12, 12, 12), 32),
+                                    ((20, 24, 28), 200), ((9, 10, 11, 12), 256)])
 def test_cp_grad_matches_oracle(dtype, dims, R):
     announce("cp_grad", dims, R, dtype)
     X, _ = inputs.noisy_low_rank(dims, R, seed_factors=9, seed_noise=10, eta=0.05, dtype=torch.float64)

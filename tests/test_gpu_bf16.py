@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_cases import TOL, announce, make_case, oracle_abs_all_modes, rel_err, rel_err_abs
+from bf16_variants import VARIANT_CASES
+from gpu_cases import TOL, announce, make_case, rel_err
 from oracle import oracle as O
 from paper_1708_08976_amd import _abi, inputs
 
@@ -60,7 +61,6 @@ def test_mttkrp_split_bf16_all_modes(dims, R):
     announce("mttkrp bf16x2", dims, R)
     X, U, planes = pair_case(dims, R, seed=sum(dims) + 7 * R)
     refs = oracle_pair_all_modes(planes, dims, U)
-    absr = oracle_abs_all_modes(X, dims, U)
     Pd, Ud = planes.cuda(), [u.cuda() for u in U]
     for n in range(len(dims)):
         out = torch.full((dims[n], R), float("nan"), device="cuda")
@@ -68,7 +68,7 @@ def test_mttkrp_split_bf16_all_modes(dims, R):
         torch.cuda.synchronize()
         got = out.cpu().numpy()
         assert np.isfinite(got).all(), "unwritten output entries, mode %d" % n
-        err = rel_err_abs(got, refs[n], absr[n])
+        err = rel_err(got, refs[n])
         assert err <= TOL["bf16x2"], (dims, R, n, err)
 
 
@@ -141,3 +141,28 @@ def test_split_bf16_exact_products():
         ref = O.mttkrp(Xh, dims, [u.numpy() for u in U], n)
         got = _abi.mttkrp(Pd, dims, Ud, n, dtype=_abi.CPM_BF16X2).cpu().numpy()
         assert rel_err(got, ref) <= 2e-6, n
+
+
+@pytest.mark.parametrize("dims,R,mode,name", VARIANT_CASES, ids=[c[3] for c in VARIANT_CASES])
+def test_split_bf16_lo_plane_is_used_by_every_variant(dims, R, mode, name):
+    """One case per kernel variant, chosen so that the tensor's lo plane
+    carries more than the tolerance: the oracle's result with the lo plane
+    zeroed differs from the pair result by over 10x the 1e-4 bound, so a
+    variant that lost the lo products would fail the first check.  The
+    kernel is then run on the hi plane alone and must match the oracle on
+    those values (it reads what it is given, not a cached plane)."""
+    announce("bf16x2 lo plane", name, dims, R, mode)
+    X, U, planes = pair_case(dims, R, seed=sum(dims) + 3 * R + mode)
+    I = X.numel()
+    hi_only = planes.clone()
+    hi_only[I:] = 0
+    Uh = [u.numpy() for u in U]
+    ref = O.mttkrp(planes.numpy().view(np.uint16), dims, Uh, mode, xtype=O.BF16PAIR)
+    ref_hi = O.mttkrp(hi_only.numpy().view(np.uint16), dims, Uh, mode, xtype=O.BF16PAIR)
+    assert rel_err(ref_hi, ref) > 10 * TOL["bf16x2"]
+    Ud = [u.cuda() for u in U]
+    got = _abi.mttkrp(planes.cuda(), dims, Ud, mode, dtype=_abi.CPM_BF16X2).cpu().numpy()
+    assert rel_err(got, ref) <= TOL["bf16x2"], rel_err(got, ref)
+    got_hi = _abi.mttkrp(hi_only.cuda(), dims, Ud, mode, dtype=_abi.CPM_BF16X2).cpu().numpy()
+    assert rel_err(got_hi, ref_hi) <= TOL["bf16x2"]
+    assert rel_err(got_hi, ref) > TOL["bf16x2"]

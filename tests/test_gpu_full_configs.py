@@ -224,3 +224,38 @@ def test_config5_64p5_mttkrp_all_with_reuse_sampled_rows(dtype):
     got = [o.cpu().numpy() for o in outs]
     check_sampled(got, X.cpu().numpy().ravel(), dims, [u.cpu().numpy().astype(np.float64) for u in U],
                   TOL[dtype], "64^5 mttkrp_all %s" % dtype)
+
+
+@pytest.mark.parametrize("dims,R,dtype", [((64,) * 5, 32, "f32"), ((64,) * 5, 128, "f32"),
+                                          ((64,) * 5, 128, "bf16x2"),
+                                          ((256, 256, 512, 32), 64, "f32"),
+                                          ((256, 256, 512, 32), 128, "bf16x2")])
+@pytest.mark.timeout(600)
+def test_closed_form_whole_output_full_size(dims, R, dtype):
+    """X = [[U]] exactly (a float64 rank-R model, stored as float32 or as its
+    bf16 pair): every row of every mode equals U_n times the Hadamard
+    product of the other Grams, a fact of the CP model that needs no oracle
+    pass, so the whole output -- every row tile, column block and split-K
+    slice of the launches the benchmark times -- is checked.  The stored
+    tensor differs from the model by its rounding (2^-24 relative per entry
+    for float32, 2^-17 for the pair), which moves M by far less than the
+    tolerance: the model's MTTKRP adds its terms coherently."""
+    announce("closed form", dims, R, dtype)
+    U64 = inputs.normal_factors(dims, R, seed=R + len(dims), device="cuda", dtype=torch.float64)
+    X = inputs.cp_model_tensor(U64).float()
+    if dtype == "bf16x2":
+        Xd, code = _abi.split_bf16(X.reshape(-1)), _abi.CPM_BF16X2
+        del X
+    else:
+        Xd, code = X, _abi.CPM_F32
+    U = [u.float() for u in U64]
+    Uh = [u.cpu().numpy() for u in U64]
+    got = gpu_all_modes(Xd, dims, U, dtype=code)
+    for n in range(len(dims)):
+        H = np.ones((R, R))
+        for k in range(len(dims)):
+            if k != n:
+                H *= Uh[k].T @ Uh[k]
+        e = rel_err(got[n], Uh[n] @ H)
+        print("closed form %s R=%d %s mode %d: relative error %.3e" % (dims, R, dtype, n, e), flush=True)
+        assert e <= TOL[dtype], (n, e)

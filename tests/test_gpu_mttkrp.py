@@ -3,8 +3,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_cases import (TOL, announce, make_case, oracle_abs_all_modes, oracle_all_modes, rel_err,
-                       rel_err_abs)
+from gpu_cases import (CANCELLATION_CASES, CANCELLATION_MIN_RATIO, TOL, announce, make_case, oracle_all_modes,
+                       rel_err, rel_err_abs)
 from oracle import oracle as O
 from paper_1708_08976_amd import _abi, inputs
 
@@ -43,7 +43,6 @@ def test_mttkrp_f32_all_modes(dims, R):
     announce("mttkrp f32", dims, R)
     X, U = make_case(dims, R, seed=sum(dims) + R)
     refs = oracle_all_modes(X, dims, U)
-    absr = oracle_abs_all_modes(X, dims, U)
     Xd, Ud = X.cuda(), [u.cuda() for u in U]
     for n in range(len(dims)):
         out = torch.full((dims[n], R), float("nan"), device="cuda")
@@ -51,21 +50,40 @@ def test_mttkrp_f32_all_modes(dims, R):
         torch.cuda.synchronize()
         got = out.cpu().numpy()
         assert np.isfinite(got).all(), "unwritten output entries, mode %d" % n
-        err = rel_err_abs(got, refs[n], absr[n])
+        if (dims, R, n) in CANCELLATION_CASES:
+            absr = O.mttkrp(np.abs(X.numpy().ravel()), dims, [np.abs(u.numpy()) for u in U], n)
+            assert np.linalg.norm(absr) >= CANCELLATION_MIN_RATIO * np.linalg.norm(refs[n])
+            err = rel_err_abs(got, refs[n], absr)
+        else:
+            err = rel_err(got, refs[n])
         assert err <= TOL["f32"], (dims, R, n, err)
 
 
+def test_config1_fp64_60x50x40_r8_every_mode():
+    """The 60x50x40 FP64 workload (entries uniform[0,1), seed 1; factors
+    N(0,1), seed 2): every mode within 1e-12 of the oracle, normwise."""
+    dims, R = (60, 50, 40), 8
+    X = inputs.uniform_tensor(dims, seed=1, dtype=torch.float64)
+    U = inputs.normal_factors(dims, R, seed=2, dtype=torch.float64)
+    refs = oracle_all_modes(X, dims, U)
+    Xd, Ud = X.cuda(), [u.cuda() for u in U]
+    for n in range(3):
+        got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
+        err = rel_err(got, refs[n])
+        print("60x50x40 fp64 mode %d: relative error %.3e" % (n, err), flush=True)
+        assert err <= TOL["f64"], (n, err)
+
+
 @pytest.mark.parametrize("dims", [(60, 50, 40), (7, 9, 11, 5), (23, 40, 3)])
-@pytest.mark.parametrize("R", [8, 33, 128])
+@pytest.mark.parametrize("R", [8, 33, 128, 200, 256])
 def test_mttkrp_f64_all_modes(dims, R):
     announce("mttkrp f64", dims, R)
     X, U = make_case(dims, R, seed=3 + R, dtype=torch.float64)
     refs = oracle_all_modes(X, dims, U)
-    absr = oracle_abs_all_modes(X, dims, U)
     Xd, Ud = X.cuda(), [u.cuda() for u in U]
     for n in range(len(dims)):
         got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
-        assert rel_err_abs(got, refs[n], absr[n]) <= TOL["f64"], (dims, R, n)
+        assert rel_err(got, refs[n]) <= TOL["f64"], (dims, R, n)
 
 
 @pytest.mark.parametrize("R", [200, 256])
@@ -74,22 +92,20 @@ def test_mttkrp_f32_wide_rank_column_blocks(R):
     announce("mttkrp wide", dims, R)
     X, U = make_case(dims, R, seed=R)
     refs = oracle_all_modes(X, dims, U)
-    absr = oracle_abs_all_modes(X, dims, U)
     Xd, Ud = X.cuda(), [u.cuda() for u in U]
     for n in range(3):
         got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
-        assert rel_err_abs(got, refs[n], absr[n]) <= TOL["f32"], n
+        assert rel_err(got, refs[n]) <= TOL["f32"], n
 
 
 def test_long_left_product_uses_several_chunks():
     dims = (33, 47, 3, 2)  # IL for the last mode = 4653 > one l-chunk
     X, U = make_case(dims, 24, seed=77)
     refs = oracle_all_modes(X, dims, U)
-    absr = oracle_abs_all_modes(X, dims, U)
     Xd, Ud = X.cuda(), [u.cuda() for u in U]
     for n in range(4):
         got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
-        assert rel_err_abs(got, refs[n], absr[n]) <= TOL["f32"]
+        assert rel_err(got, refs[n]) <= TOL["f32"]
 
 
 def test_unaligned_base_pointer():
@@ -100,10 +116,9 @@ def test_unaligned_base_pointer():
     Xd = big.cuda()[1:]  # 4-byte offset: 16-byte vector loads must be avoided
     Ud = [u.cuda() for u in U]
     refs = oracle_all_modes(X, dims, U)
-    absr = oracle_abs_all_modes(X, dims, U)
     for n in range(3):
         got = _abi.mttkrp(Xd, dims, Ud, n).cpu().numpy()
-        assert rel_err_abs(got, refs[n], absr[n]) <= TOL["f32"]
+        assert rel_err(got, refs[n]) <= TOL["f32"]
 
 
 def test_bitwise_reproducible():
@@ -190,11 +205,10 @@ def test_many_blocks_per_work_group(dtype, R):
     else:
         planes = inputs.split_bf16_planes(X)
         Xd, code, xh, xt = planes.cuda(), _abi.CPM_BF16X2, planes.numpy().view(np.uint16), O.BF16PAIR
-    absr = oracle_abs_all_modes(X, dims, U)
     for n in range(3):
         ref = O.mttkrp(xh, dims, [u.numpy() for u in U], n, xtype=xt)
         got = _abi.mttkrp(Xd, dims, Ud, n, dtype=code).cpu().numpy()
-        assert rel_err_abs(got, ref, absr[n]) <= TOL[dtype], (n, R)
+        assert rel_err(got, ref) <= TOL[dtype], (n, R)
 
 
 @pytest.mark.parametrize("dims", [(4096, 300), (2048, 500, 3), (8192, 96, 2)])
@@ -206,6 +220,5 @@ def test_wide_output_long_resident_chunk(dims, R):
     announce("wide output", dims, R)
     X, U = make_case(dims, R, seed=R + len(dims))
     ref = O.mttkrp(X.numpy().ravel(), dims, [u.numpy() for u in U], 0)
-    absr = O.mttkrp(np.abs(X.numpy().ravel()), dims, [np.abs(u.numpy()) for u in U], 0)
     got = _abi.mttkrp(X.cuda(), dims, [u.cuda() for u in U], 0).cpu().numpy()
-    assert rel_err_abs(got, ref, absr) <= TOL["f32"]
+    assert rel_err(got, ref) <= TOL["f32"]

@@ -1,0 +1,51 @@
+"""mttkrp_scratch, the MTTKRP entry point that allocates nothing (its
+split-K partials go to the library's fixed scratch array), against mttkrp
+with a caller workspace and against the FP64 oracle: two calls in a row,
+the second on a smaller tensor, for every mode and each element type."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import TOL, announce, make_case, rel_err
+from oracle import oracle as O
+from paper_1708_08976_amd import _abi, inputs
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "f32": [((160, 150, 140), 32), ((37, 29, 41), 13)],
+    "f64": [((96, 90, 80), 24), ((23, 40, 3), 8)],
+    "bf16x2": [((160, 150, 140), 64), ((64, 48, 80), 32)],
+}
+
+
+def run_case(dims, R, kind, seed):
+    tdt = torch.float64 if kind == "f64" else torch.float32
+    X, U = make_case(dims, R, seed=seed, dtype=tdt)
+    Ud = [u.cuda() for u in U]
+    Uh = [u.numpy() for u in U]
+    if kind == "bf16x2":
+        planes = inputs.split_bf16_planes(X)
+        Xd, code, Xh, xt = planes.cuda(), _abi.CPM_BF16X2, planes.numpy().view(np.uint16), O.BF16PAIR
+    else:
+        code = _abi.CPM_F64 if kind == "f64" else _abi.CPM_F32
+        Xd, Xh, xt = X.cuda(), X.numpy().ravel(), None
+    for n in range(len(dims)):
+        announce("mttkrp_scratch", kind, dims, R, "mode", n,
+                 "partials", _abi.mttkrp_workspace_bytes(dims, R, n, code))
+        out = torch.full((dims[n], R), float("nan"), dtype=tdt, device="cuda")
+        _abi.mttkrp_scratch(Xd, dims, Ud, n, out=out, dtype=code)
+        want = _abi.mttkrp(Xd, dims, Ud, n, dtype=code)
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), (kind, dims, n)
+        ref = O.mttkrp(Xh, dims, Uh, n, xtype=xt)
+        assert rel_err(out.cpu().numpy(), ref) <= TOL[kind], (kind, dims, n)
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64", "bf16x2"])
+def test_mttkrp_scratch_two_calls_second_smaller(kind):
+    (d1, r1), (d2, r2) = CASES[kind]
+    assert any(_abi.mttkrp_workspace_bytes(d1, r1, n, _abi.CPM_F32) > 0 for n in range(3))
+    run_case(d1, r1, kind, seed=101)
+    run_case(d2, r2, kind, seed=202)
+
