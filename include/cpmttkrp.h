@@ -109,6 +109,26 @@ cpm_status mttkrp(const void *X, const int64_t *dims, int N, const void *const *
                   hipStream_t stream);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): `mttkrp` without
+ * a workspace argument.  The split-K partial results go to a fixed device
+ * array of CPM_SCRATCH_BYTES bytes inside the library (one per GPU, held
+ * until the process ends), so the call allocates nothing and launches the
+ * same kernels with the same tiling as `mttkrp` -- the result is bitwise
+ * equal to mttkrp's.  Arguments as for `mttkrp`.  Shapes whose partial
+ * results exceed CPM_SCRATCH_BYTES (cpm_mttkrp_workspace_bytes tells)
+ * return CPM_EUNSUPPORTED before any launch.  Every call on one GPU uses
+ * the same array: calls that overlap on one GPU (concurrent streams or
+ * threads) race and give wrong results; serialise them.  Nothing in the
+ * array needs clearing between calls (every partial read is written first
+ * by the same call).  The first call on a device looks up the array's
+ * device address (hipGetSymbolAddress) with that device current.
+ */
+#define CPM_SCRATCH_BYTES (64u << 20)
+cpm_status mttkrp_scratch(const void *X, const int64_t *dims, int N, const void *const *factors, int R, int mode,
+                          void *out, cpm_dtype dt, hipStream_t stream);
+
+/*
  * Diagnostics: writes into buf (at most len bytes, NUL-terminated) the
  * kernel and launch shape `mttkrp` would use for this shape, mode, rank and
  * type -- the contraction kernel with its template parameters, its grid,

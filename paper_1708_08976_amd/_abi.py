@@ -17,8 +17,8 @@ CPM_F32, CPM_F64, CPM_BF16X2 = 0, 1, 2
 STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_EUNSUPPORTED", 3: "CPM_ENOTPD",
                 4: "CPM_EHIP", 5: "CPM_EWORKSPACE"}
 
-EXPORTS = ["cpm_version", "cpm_last_error", "cpm_mttkrp_workspace_bytes", "mttkrp", "cpm_mttkrp_describe",
-           "cpm_mttkrp_all_workspace_bytes", "mttkrp_all",
+EXPORTS = ["cpm_version", "cpm_last_error", "cpm_mttkrp_workspace_bytes", "mttkrp", "mttkrp_scratch",
+           "cpm_mttkrp_describe", "cpm_mttkrp_all_workspace_bytes", "mttkrp_all",
            "cpm_residual2_workspace_bytes", "cpm_residual2",
            "cpm_cp_als_workspace_bytes", "cpm_cp_grad_workspace_bytes", "cp_als_step", "cp_grad",
            "cpm_xnorm2_workspace_bytes", "cpm_xnorm2", "cpm_split_bf16", "cpm_krp_rows"]
@@ -51,6 +51,8 @@ def load():
     lib.cpm_mttkrp_workspace_bytes.restype = sz
     lib.mttkrp.argtypes = [vp, i64p, ci, vpp, ci, ci, vp, ci, vp, sz, vp]
     lib.mttkrp.restype = ci
+    lib.mttkrp_scratch.argtypes = [vp, i64p, ci, vpp, ci, ci, vp, ci, vp]
+    lib.mttkrp_scratch.restype = ci
     lib.cpm_mttkrp_describe.argtypes = [i64p, ci, ci, ci, ci, vp, ctypes.c_char_p, sz]
     lib.cpm_mttkrp_describe.restype = ci
     lib.cpm_mttkrp_all_workspace_bytes.argtypes = [i64p, ci, ci, ci]
@@ -150,6 +152,25 @@ def mttkrp(X, dims, factors, mode, out=None, dtype=None, workspace=None, stream=
     ws_len = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(lib.mttkrp(X.data_ptr(), _dims(dims), len(dims), _ptrs(factors), R, int(mode), out.data_ptr(), dt,
                       ws_ptr, ws_len, _stream(X.device, stream)))
+    return out
+
+
+def mttkrp_scratch(X, dims, factors, mode, out=None, dtype=None, stream=None):
+    """mttkrp with the library's built-in scratch array for its partial
+    results (no workspace, nothing allocated by the library)."""
+    lib = load()
+    dt = _dtype_code(X, dtype)
+    _require(X, "X")
+    R = int(next(f for f in factors if f is not None).shape[1])
+    fdt = torch.float64 if dt == CPM_F64 else torch.float32
+    for k, f in enumerate(factors):
+        if f is not None and k != mode:
+            _require(f, "factors[%d]" % k)
+    if out is None:
+        out = torch.empty((int(dims[mode]), R), dtype=fdt, device=X.device)
+    _require(out, "out")
+    _check(lib.mttkrp_scratch(X.data_ptr(), _dims(dims), len(dims), _ptrs(factors), R, int(mode), out.data_ptr(),
+                              dt, _stream(X.device, stream)))
     return out
 
 

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -18,6 +19,13 @@
 #include "tree_kernels.hpp"
 
 using namespace cpm;
+
+// Split-K partials of mttkrp_scratch: a fixed device array, one copy per
+// GPU, alive until the process ends.  In host code this name is only a
+// stand-in for the symbol; the device address comes from
+// hipGetSymbolAddress (scratch_ptr below) and is the only form of it that
+// is ever passed to a kernel.
+static __device__ __align__(256) unsigned char scratch[CPM_SCRATCH_BYTES];
 
 namespace {
 
@@ -1177,6 +1185,27 @@ cpm_status check_lds_for_cholesky(int R) {
     return CPM_OK;
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and cached.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+cpm_status scratch_ptr(void **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CPM_EUNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(CPM_EHIP, "hipGetSymbolAddress gave a null address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CPM_OK;
+}
+
 }  // namespace
 
 // ================================ C-ABI ====================================
@@ -1244,6 +1273,27 @@ int cpm_mttkrp_describe(const int64_t *dims, int N, int R, int mode, cpm_dtype d
              name, (long long)p.ntiles, (long long)(p.S * p.nlc), p.ncb, p.lds, p.LC, p.SPB, (long long)p.G_in,
              (long long)p.n_outer, (long long)p.S, (long long)p.nlc, (int)p.reduce);
     return CPM_OK;
+}
+
+cpm_status mttkrp_scratch(const void *X, const int64_t *dims, int N, const void *const *factors, int R, int mode,
+                          void *out, cpm_dtype dt, hipStream_t stream) {
+    int64_t total;
+    cpm_status s = validate_mttkrp(X, dims, N, factors, R, mode, out, dt, &total);
+    if (s) return s;
+    Plan p = make_plan(dims, N, R, mode, dt, X);
+    if (p.max_offset >= kMaxBufferOffset)
+        return fail(CPM_EUNSUPPORTED, "mode %d: entries %lld apart along mode %d exceed the 4 GiB reach of one "
+                    "buffer resource", mode, (long long)p.IL, mode);
+    const size_t need = align_up(p.partial_bytes);
+    if (need > (size_t)CPM_SCRATCH_BYTES)
+        return fail(CPM_EUNSUPPORTED, "this MTTKRP needs %zu bytes of partial results, above the %zu-byte scratch "
+                    "array; call mttkrp with a workspace", need, (size_t)CPM_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if (need > 0) {
+        s = scratch_ptr(&ws);
+        if (s) return s;
+    }
+    return run_mttkrp(p, X, dims, N, factors, R, mode, out, dt, ws, stream);
 }
 
 size_t cpm_mttkrp_all_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {

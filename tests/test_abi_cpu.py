@@ -130,6 +130,32 @@ def test_solver_entry_points_validate():
     assert lib.cpm_residual2(FAKE, big, 3, _ptrs(3), 64, 0, FAKE, FAKE, 1 << 40, None) == _abi.CPM_EUNSUPPORTED
 
 
+def test_mttkrp_scratch_validates_before_any_device_call():
+    """The entry point without a workspace: bad arguments and shapes whose
+    partial results exceed the built-in scratch array are rejected before
+    any HIP call (so this runs without a GPU)."""
+    lib = _abi.load()
+
+    def call(dims, R=8, mode=0, X=FAKE, out=FAKE, dt=0, factors=None):
+        f = factors if factors is not None else _ptrs(len(dims))
+        return lib.mttkrp_scratch(X, _dims(dims), len(dims), f, R, mode, out, dt, None)
+
+    assert call((4, 5, 6), X=None) == _abi.CPM_EINVAL
+    assert call((4, 5, 6), out=None) == _abi.CPM_EINVAL
+    assert call((4, 5, 6), mode=3) == _abi.CPM_EINVAL
+    assert call((4, 5, 6), R=257) == _abi.CPM_EUNSUPPORTED
+    assert call((4, 5, 6), factors=_ptrs(3, null_at=2)) == _abi.CPM_EINVAL
+    need = _abi.mttkrp_workspace_bytes((4096, 4096, 64), 256, 0, _abi.CPM_F32)
+    assert need > 64 << 20
+    assert call((4096, 4096, 64), R=256, mode=0) == _abi.CPM_EUNSUPPORTED
+    assert "scratch" in _abi.last_error()
+    # every benchmark workload fits the scratch array
+    for dims, R in [((512, 512, 512), 32), ((256, 256, 512, 32), 128), ((64,) * 5, 128)]:
+        for dt in (_abi.CPM_F32, _abi.CPM_BF16X2):
+            for n in range(len(dims)):
+                assert _abi.mttkrp_workspace_bytes(dims, R, n, dt) <= 64 << 20
+
+
 def test_describe_names_the_kernel_and_launch():
     d = _abi.describe((512, 512, 512), 32, 1, _abi.CPM_F32)
     assert d.startswith("k_left32<NC=1,WM=1>") and "grid=" in d
