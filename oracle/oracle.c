@@ -154,6 +154,89 @@ int oracle_mttkrp(const void *X, int xtype, const int64_t *dims, int N,
 }
 
 /*
+ * Symmetric-pair packed storage.  A tensor whose first two modes have equal
+ * size n and X(i, j, rest) = X(j, i, rest) is stored as its triangle i <= j:
+ * the pair (i, j) becomes one index p = j (j + 1) / 2 + i (i fastest, then
+ * j, the natural linearisation restricted to the triangle), and the packed
+ * tensor has modes (p, I_2, ..., I_{N-1}) in natural order, P = n (n + 1) / 2
+ * pairs.  Section 5.3.3 stores the region-by-region correlation pair of its
+ * fMRI tensor this way (as one linearised triangle of about half the
+ * entries); the diagonal is kept here so the packed tensor represents the
+ * whole symmetric tensor.
+ *
+ * Pair (i, j) of packed index p.
+ */
+static void pair_of(int64_t p, int64_t *i, int64_t *j)
+{
+    int64_t jj = 0;
+    while ((jj + 1) * (jj + 2) / 2 <= p) ++jj;
+    *j = jj;
+    *i = p - jj * (jj + 1) / 2;
+}
+
+/*
+ * Mode-n MTTKRP of the full symmetric tensor represented by the packed
+ * tensor Xp, from the definition of Section 2.2: every packed entry stands
+ * for the full-tensor entries (i, j, rest) and, when i != j, (j, i, rest),
+ * each of which adds X * prod_{k != n} U_k(idx_k, :) to row idx_n.
+ * dims are the full tensor's (dims[0] == dims[1]); out is I_n x R.
+ */
+int oracle_mttkrp_sympair(const void *Xp, int xtype, const int64_t *dims, int N,
+                          const double *const *U, int R, int mode, double *out, int nthreads)
+{
+    int64_t total;
+    if (!Xp || !U || !out || N < 3 || !check_dims(dims, N, R, &total) || mode < 0 || mode >= N ||
+        dims[0] != dims[1])
+        return OR_EINVAL;
+    const int64_t n = dims[0], P = n * (n + 1) / 2;
+    const int64_t rest = total / (n * n), ptotal = P * rest;
+    int T = num_threads(nthreads);
+    int64_t In = dims[mode];
+    double *priv = (double *)calloc((size_t)T * (size_t)In * (size_t)R, sizeof(double));
+    if (!priv) return OR_ENOMEM;
+#pragma omp parallel num_threads(T)
+    {
+#ifdef _OPENMP
+        int t = omp_get_thread_num();
+        int nt = omp_get_num_threads();
+#else
+        int t = 0, nt = 1;
+#endif
+        int64_t chunk = (ptotal + nt - 1) / nt;
+        int64_t lo = (int64_t)t * chunk, hi = lo + chunk < ptotal ? lo + chunk : ptotal;
+        double *acc = priv + (size_t)t * (size_t)In * (size_t)R;
+        double *w = (double *)malloc(sizeof(double) * (size_t)R);
+        int64_t idx[64];
+        for (int64_t l = lo; l < hi; ++l) {
+            double x = load_entry(Xp, xtype, ptotal, l);
+            int64_t i, j;
+            pair_of(l % P, &i, &j);
+            decode(l / P, dims + 2, N - 2, idx + 2);
+            for (int copy = 0; copy < (i == j ? 1 : 2); ++copy) {
+                idx[0] = copy ? j : i;
+                idx[1] = copy ? i : j;
+                for (int c = 0; c < R; ++c) w[c] = x;
+                for (int k = 0; k < N; ++k) {
+                    if (k == mode) continue;
+                    const double *row = U[k] + idx[k] * R;
+                    for (int c = 0; c < R; ++c) w[c] *= row[c];
+                }
+                double *o = acc + idx[mode] * R;
+                for (int c = 0; c < R; ++c) o[c] += w[c];
+            }
+        }
+        free(w);
+    }
+    for (int64_t e = 0; e < In * R; ++e) {
+        double s = 0.0;
+        for (int t = 0; t < T; ++t) s += priv[(size_t)t * (size_t)In * (size_t)R + e];
+        out[e] = s;
+    }
+    free(priv);
+    return OR_OK;
+}
+
+/*
  * Selected rows of the mode-n MTTKRP: out[q][c] = M(rows[q], c).  Each row
  * is a sum over the entries whose mode-n index equals rows[q]; this serves
  * sampled checks on tensors too large for a full oracle pass.

@@ -44,6 +44,8 @@ def _load():
     dpp = ctypes.POINTER(ctypes.c_void_p)
     lib.oracle_mttkrp.argtypes = [P, ctypes.c_int, i64p, ctypes.c_int, dpp, ctypes.c_int,
                                   ctypes.c_int, P, ctypes.c_int]
+    lib.oracle_mttkrp_sympair.argtypes = [P, ctypes.c_int, i64p, ctypes.c_int, dpp, ctypes.c_int,
+                                          ctypes.c_int, P, ctypes.c_int]
     lib.oracle_mttkrp_rows.argtypes = [P, ctypes.c_int, i64p, ctypes.c_int, dpp, ctypes.c_int,
                                        ctypes.c_int, i64p, ctypes.c_int64, P, ctypes.c_int]
     lib.oracle_krp_rows.argtypes = [dpp, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
@@ -111,6 +113,23 @@ def mttkrp(X, dims, factors, mode, xtype=None, nthreads=None):
     out = np.zeros((int(d[mode]), R), dtype=np.float64)
     st = lib.oracle_mttkrp(X.ctypes.data, xtype, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                            len(d), _ptrs(U), R, mode, out.ctypes.data, _threads(nthreads))
+    if st:
+        raise OracleError(st)
+    return out
+
+
+def mttkrp_sympair(Xp, dims, factors, mode, xtype=None, nthreads=None):
+    """Mode-``mode`` MTTKRP of the full symmetric tensor (dims[0] ==
+    dims[1], X(i,j,..) = X(j,i,..)) given as its packed triangle i <= j:
+    pair index p = j(j+1)/2 + i fastest, then modes 2..N-1 (float64)."""
+    lib = _load()
+    Xp, xtype = _xarg(Xp, xtype)
+    d = _dims(dims)
+    U = _factors(factors)
+    R = U[0].shape[1]
+    out = np.zeros((int(d[mode]), R), dtype=np.float64)
+    st = lib.oracle_mttkrp_sympair(Xp.ctypes.data, xtype, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   len(d), _ptrs(U), R, mode, out.ctypes.data, _threads(nthreads))
     if st:
         raise OracleError(st)
     return out

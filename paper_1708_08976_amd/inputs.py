@@ -100,6 +100,34 @@ def symmetric_pair_tensor(dims, seed, device="cpu", dtype=torch.float32):
     return x.contiguous().to(dtype)
 
 
+def sympair_count(n):
+    """Pairs (i, j) with i <= j < n: the packed length of a symmetric pair
+    of modes of size n."""
+    return n * (n + 1) // 2
+
+
+def sympair_indices(n, device="cpu"):
+    """(i, j) of every packed pair index p = j (j + 1) / 2 + i, i <= j, in
+    order of p: i fastest, then j (the natural linearisation restricted to
+    the triangle)."""
+    j = torch.repeat_interleave(torch.arange(n, device=device), torch.arange(1, n + 1, device=device))
+    start = j * (j + 1) // 2
+    i = torch.arange(sympair_count(n), device=device) - start
+    return i, j
+
+
+def pack_sympair(x, dims):
+    """Packed triangle of a tensor symmetric in modes 0 and 1 (torch layout
+    in, torch layout out): entry (p, i_2, ..., i_{N-1}) of the result is
+    X(i_p, j_p, i_2, ...).  The result has torch shape
+    (I_{N-1}, ..., I_2, P).  Pure data movement."""
+    n = int(dims[0])
+    assert int(dims[1]) == n
+    i, j = sympair_indices(n, device=x.device)
+    # torch layout: the last two axes are modes 1 and 0
+    return x[..., j, i].contiguous()
+
+
 def split_bf16_planes(x):
     """hi = bf16(x) and lo = bf16(x - hi), both round-to-nearest-even,
     returned as one uint16-compatible int16 tensor holding the hi plane

@@ -293,3 +293,86 @@ def test_residual2_widens_bf16_pairs_exactly():
     as32 = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
     val = as32[:60] + as32[60:]
     assert O.residual2(bits, dims, U, xtype=O.BF16PAIR) == O.residual2(val, dims, U)
+
+
+# ---------------------------------------------------------------------------
+# Symmetric-pair packed storage (Section 5.3.3 stores the symmetric region
+# pair of its fMRI tensor as one linearised triangle).
+# ---------------------------------------------------------------------------
+def _symmetric_full(dims, seed):
+    """A tensor symmetric in modes 0 and 1, in natural storage order."""
+    r = np.random.default_rng(seed)
+    A = r.standard_normal(tuple(reversed(dims)))  # torch layout: [..., j, i]
+    return (A + np.swapaxes(A, -1, -2)).ravel()
+
+
+def _pack(Xfull, dims):
+    import torch
+    from paper_1708_08976_amd import inputs
+    x = torch.from_numpy(np.asarray(Xfull).reshape(tuple(reversed(dims))))
+    return inputs.pack_sympair(x, dims).numpy().ravel()
+
+
+def test_sympair_layout_by_hand():
+    """n = 3: packed order (0,0), (0,1), (1,1), (0,2), (1,2), (2,2), pair
+    index fastest, then the next mode."""
+    dims = (3, 3, 2)
+    vals = {}
+    full = np.zeros(18)
+    for r in range(2):
+        for i in range(3):
+            for j in range(i, 3):
+                v = 100 * r + 10 * i + j
+                full[i + 3 * j + 9 * r] = v
+                full[j + 3 * i + 9 * r] = v
+    want = [0, 1, 11, 2, 12, 22, 100, 101, 111, 102, 112, 122]
+    assert list(_pack(full, dims)) == want
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 2), (4, 4, 3, 2), (2, 2, 1), (5, 5, 2, 1, 3), (1, 1, 4)])
+@pytest.mark.parametrize("R", [1, 4])
+def test_sympair_oracle_matches_brute_force_of_the_full_tensor(dims, R):
+    """The packed-storage oracle equals the explicit unfolding times the
+    explicit Khatri-Rao product of the unpacked symmetric tensor, every
+    mode (pair modes included)."""
+    X = _symmetric_full(dims, 5 + R)
+    Xp = _pack(X, dims)
+    U = _factors(dims, R, 6 + R)
+    for n in range(len(dims)):
+        got = O.mttkrp_sympair(Xp, dims, U, n)
+        ref = brute.mttkrp(X, dims, U, n)
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * max(1.0, np.abs(ref).max()))
+
+
+def test_sympair_ones_counts_the_diagonal_once():
+    """All-ones packed tensor and factors: row i of mode n counts the full
+    tensor's entries with index i in mode n, prod_{k != n} I_k; a diagonal
+    pair counted twice (or an off-diagonal one once) changes the count."""
+    dims = (4, 4, 3)
+    P = 10
+    Xp = np.ones(P * 3)
+    U = [np.ones((d, 2)) for d in dims]
+    for n in range(3):
+        want = np.prod([d for k, d in enumerate(dims) if k != n])
+        np.testing.assert_array_equal(O.mttkrp_sympair(Xp, dims, U, n), np.full((dims[n], 2), want))
+
+
+def test_sympair_closed_form_symmetric_exact_rank():
+    """X = [[A, A, U_2, U_3]] is symmetric in modes 0 and 1; its packed
+    triangle gives MTTKRP_n = U_n * (Hadamard product of the other Grams)."""
+    dims, R = (5, 5, 3, 4), 3
+    U = _factors(dims, R, 17)
+    U[1] = U[0]
+    X = brute.cp_tensor(U)
+    Xp = _pack(X, dims)
+    for n in range(4):
+        H = np.ones((R, R))
+        for k in range(4):
+            if k != n:
+                H *= U[k].T @ U[k]
+        np.testing.assert_allclose(O.mttkrp_sympair(Xp, dims, U, n), U[n] @ H, rtol=1e-11, atol=1e-11)
+
+
+def test_sympair_rejects_unequal_pair_modes():
+    with pytest.raises(O.OracleError):
+        O.mttkrp_sympair(np.ones(12), (3, 4, 2), _factors((3, 4, 2), 2, 1), 0)
