@@ -168,6 +168,46 @@ cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *con
                       hipStream_t stream);
 
 /*
+ * Symmetric-pair packed storage (Section 5.3.3 stores the symmetric
+ * region-by-region pair of its fMRI tensor as one linearised triangle).
+ * A tensor with I_0 = I_1 = n and X(i, j, rest) = X(j, i, rest) is held as
+ * its triangle i <= j: pair index p = j (j + 1) / 2 + i (i fastest, then j),
+ * followed by modes 2..N-1 in natural order, P = n (n + 1) / 2 pairs, so
+ * about half the entries.  The diagonal is kept, so the packed tensor
+ * stands for the whole symmetric tensor: a packed entry is the value of
+ * (i, j, rest) and, when i != j, of (j, i, rest).  For CPM_BF16X2 the
+ * packed tensor is two planes (hi then lo) of P * I_2 * ... entries.
+ * dims are the full tensor's; N >= 3; dims[0] == dims[1] (else
+ * CPM_EINVAL).
+ */
+size_t cpm_sympair_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);
+
+/*
+ * MTTKRPs (Section 2.2) of the full symmetric tensor held packed in Xp, for
+ * every mode n with outs[n] non-null (device I_n x R; null skips the mode);
+ * results equal `mttkrp` of the unpacked tensor to rounding while X is read
+ * at about half the bytes.  Modes 2..N-1 are MTTKRPs of the packed view
+ * (P, I_2, ...) with the pair factor W(p, :) = U_0(i) * U_1(j) + U_0(j) *
+ * U_1(i) (i < j; U_0(i) * U_1(i) on the diagonal) built on the fly per
+ * call; the two pair modes share one pass, the view's mode-0 MTTKRP T
+ * (P x R), and then M_0(a, :) = sum_j T(pair(a, j), :) * U_1(j, :) and
+ * M_1(b, :) = sum_i T(pair(i, b), :) * U_0(i, :).  Every factor is read.
+ * Stream-ordered; bitwise reproducible run to run.
+ */
+cpm_status mttkrp_sympair(const void *Xp, const int64_t *dims, int N, const void *const *factors, int R,
+                          void *const *outs, cpm_dtype dt, void *workspace, size_t ws_bytes,
+                          hipStream_t stream);
+
+/*
+ * Packs a full tensor symmetric in modes 0 and 1 (device X, natural order)
+ * into the triangle layout above (device Xp, P * I_2 * ... entries, or two
+ * planes of them for CPM_BF16X2).  Only entries i <= j of X are read; the
+ * symmetry itself is not checked.  Pure data movement.
+ */
+cpm_status cpm_pack_sympair(const void *X, const int64_t *dims, int N, cpm_dtype dt, void *Xp,
+                            hipStream_t stream);
+
+/*
  * Bytes of workspace `cpm_residual2` needs (0 for invalid arguments).
  */
 size_t cpm_residual2_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt);

@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_EUNSUPPORTED", 3: "CPM_ENO
 
 EXPORTS = ["cpm_version", "cpm_last_error", "cpm_mttkrp_workspace_bytes", "mttkrp", "mttkrp_scratch",
            "cpm_mttkrp_describe", "cpm_mttkrp_all_workspace_bytes", "mttkrp_all",
+           "cpm_sympair_workspace_bytes", "mttkrp_sympair", "cpm_pack_sympair",
            "cpm_residual2_workspace_bytes", "cpm_residual2",
            "cpm_cp_als_workspace_bytes", "cpm_cp_grad_workspace_bytes", "cp_als_step", "cp_grad",
            "cpm_xnorm2_workspace_bytes", "cpm_xnorm2", "cpm_split_bf16", "cpm_krp_rows"]
@@ -59,6 +60,12 @@ def load():
     lib.cpm_mttkrp_all_workspace_bytes.restype = sz
     lib.mttkrp_all.argtypes = [vp, i64p, ci, vpp, ci, vpp, ci, vp, sz, vp]
     lib.mttkrp_all.restype = ci
+    lib.cpm_sympair_workspace_bytes.argtypes = [i64p, ci, ci, ci]
+    lib.cpm_sympair_workspace_bytes.restype = sz
+    lib.mttkrp_sympair.argtypes = [vp, i64p, ci, vpp, ci, vpp, ci, vp, sz, vp]
+    lib.mttkrp_sympair.restype = ci
+    lib.cpm_pack_sympair.argtypes = [vp, i64p, ci, ci, vp, vp]
+    lib.cpm_pack_sympair.restype = ci
     lib.cpm_residual2_workspace_bytes.argtypes = [i64p, ci, ci, ci]
     lib.cpm_residual2_workspace_bytes.restype = sz
     lib.cpm_residual2.argtypes = [vp, i64p, ci, vpp, ci, ci, vp, vp, sz, vp]
@@ -212,6 +219,57 @@ def mttkrp_all(X, dims, factors, outs=None, modes=None, dtype=None, workspace=No
                           None if workspace is None else workspace.data_ptr(),
                           0 if workspace is None else workspace.numel() * workspace.element_size(),
                           _stream(X.device, stream)))
+    return outs
+
+
+def sympair_workspace_bytes(dims, R, dtype):
+    return load().cpm_sympair_workspace_bytes(_dims(dims), len(dims), int(R), int(dtype))
+
+
+def pack_sympair(X, dims, dtype=None, out=None, stream=None):
+    """Packed triangle (i <= j of modes 0 and 1) of a full symmetric tensor
+    -> flat tensor of P * I_2 * ... entries (two planes for CPM_BF16X2)."""
+    lib = load()
+    dt = _dtype_code(X, dtype)
+    _require(X, "X")
+    n = int(dims[0])
+    count = n * (n + 1) // 2
+    for d in dims[2:]:
+        count *= int(d)
+    if out is None:
+        if dt == CPM_BF16X2:
+            out = torch.empty(2 * count, dtype=torch.int16, device=X.device)
+        else:
+            out = torch.empty(count, dtype=torch.float64 if dt == CPM_F64 else torch.float32, device=X.device)
+    _require(out, "out")
+    _check(lib.cpm_pack_sympair(X.data_ptr(), _dims(dims), len(dims), dt, out.data_ptr(), _stream(X.device, stream)))
+    return out
+
+
+def mttkrp_sympair(Xp, dims, factors, outs=None, modes=None, dtype=None, workspace=None, stream=None):
+    """MTTKRPs of the full symmetric tensor held packed in Xp, for every
+    mode in `modes` (default: all) -> list of N outputs (None where skipped)."""
+    lib = load()
+    dt = _dtype_code(Xp, dtype)
+    _require(Xp, "Xp")
+    R = int(factors[0].shape[1])
+    for k, f in enumerate(factors):
+        _require(f, "factors[%d]" % k)
+    fdt = torch.float64 if dt == CPM_F64 else torch.float32
+    if outs is None:
+        want = set(range(len(dims))) if modes is None else set(modes)
+        outs = [torch.empty((int(d), R), dtype=fdt, device=Xp.device) if n in want else None
+                for n, d in enumerate(dims)]
+    for n, o in enumerate(outs):
+        if o is not None:
+            _require(o, "outs[%d]" % n)
+    need = lib.cpm_sympair_workspace_bytes(_dims(dims), len(dims), R, dt)
+    if workspace is None:
+        workspace = _workspace(need, Xp.device)
+    _check(lib.mttkrp_sympair(Xp.data_ptr(), _dims(dims), len(dims), _ptrs(factors), R, _ptrs(outs), dt,
+                              None if workspace is None else workspace.data_ptr(),
+                              0 if workspace is None else workspace.numel() * workspace.element_size(),
+                              _stream(Xp.device, stream)))
     return outs
 
 

@@ -16,6 +16,7 @@
 #include "mttkrp32_kernels.hpp"
 #include "mttkrp_kernels.hpp"
 #include "residual_kernels.hpp"
+#include "sympair_kernels.hpp"
 #include "tree_kernels.hpp"
 
 using namespace cpm;
@@ -948,6 +949,95 @@ cpm_status tree_leaf(const TreePlan &t, const int64_t *dims, int N, const void *
     return tree_leaf_t<float>(t, dims, N, factors, R, n, w, (float *)out, st);
 }
 
+// Every requested mode's MTTKRP (arguments validated, workspace laid out):
+// the two-group reuse when it pays, otherwise one ordinary MTTKRP per mode.
+cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
+                       void *const *outs, cpm_dtype dt, const AllWs &w, hipStream_t stream) {
+    cpm_status s;
+    int nwant = 0;
+    bool want_left = false, want_right = false;
+    TreePlan tree = plan_tree(dims, N, R);
+    for (int n = 0; n < N; ++n)
+        if (outs[n]) {
+            ++nwant;
+            (n < tree.s ? want_left : want_right) = true;
+        }
+    tree.use = tree.use && nwant >= 3 && tree_reach_ok(tree, X, R, dt);
+    if (tree.use) {
+        if (want_left) {
+            s = tree_pass(tree, true, X, factors, R, dt, w, stream);
+            if (s) return s;
+        }
+        if (want_right) {
+            s = tree_pass(tree, false, X, factors, R, dt, w, stream);
+            if (s) return s;
+        }
+    }
+    for (int n = 0; n < N; ++n) {
+        if (!outs[n]) continue;
+        if (tree.use) {
+            s = tree_leaf(tree, dims, N, factors, R, n, dt, w, outs[n], stream);
+        } else {
+            const Plan p = make_plan(dims, N, R, n, dt, X);
+            s = run_mttkrp(p, X, dims, N, factors, R, n, outs[n], dt, w.mws, stream);
+        }
+        if (s) return s;
+    }
+    return CPM_OK;
+}
+
+// ------------------------- symmetric-pair packed storage -------------------
+// The packed tensor viewed as an (N-1)-way tensor (P, I_2, ..., I_{N-1}).
+struct SymView {
+    int64_t n = 0, P = 0, rest = 1;
+    int NV = 0;
+    int64_t vd[CPM_MAX_MODES];
+};
+
+SymView sym_view(const int64_t *dims, int N) {
+    SymView v;
+    v.n = dims[0];
+    v.P = v.n * (v.n + 1) / 2;
+    v.NV = N - 1;
+    v.vd[0] = v.P;
+    for (int k = 2; k < N; ++k) {
+        v.vd[k - 1] = dims[k];
+        v.rest *= dims[k];
+    }
+    return v;
+}
+
+// Workspace: the pair factor W and the pair intermediate T (P x R each),
+// then the view's all-mode workspace.
+struct SymWs {
+    void *W, *T;
+    AllWs all;
+    size_t need;
+};
+
+SymWs layout_sym(const SymView &v, int R, cpm_dtype dt, char *base) {
+    SymWs w{};
+    const size_t pr = align_up((size_t)v.P * R * dtype_f_bytes(dt));
+    w.W = base;
+    w.T = base ? base + pr : nullptr;
+    w.all = layout_all(v.vd, v.NV, R, dt, base, 2 * pr);
+    w.need = 2 * pr + w.all.need;
+    return w;
+}
+
+cpm_status check_sym(const int64_t *dims, int N, int R, cpm_dtype dt) {
+    int64_t total;
+    cpm_status s = check_dtype(dt);
+    if (s) return s;
+    s = check_shape(dims, N, R, &total, CPM_MAX_RANK);
+    if (s) return s;
+    if (N < 3) return fail(CPM_EINVAL, "packed symmetric-pair storage needs N >= 3 (N=%d)", N);
+    if (dims[0] != dims[1])
+        return fail(CPM_EINVAL, "the symmetric pair needs dims[0] == dims[1] (%lld, %lld)", (long long)dims[0],
+                    (long long)dims[1]);
+    return CPM_OK;
+}
+
 // ------------------------------ residual ------------------------------------
 // X viewed as Rr rows (modes s..N-1) of L contiguous entries (modes 0..s-1);
 // s maximises the used part of a work-group's 128 x 32 output tile,
@@ -1325,36 +1415,96 @@ cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *con
         return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
     s = check_reach(X, dims, N, R, dt);
     if (s) return s;
-    const AllWs w = layout_all(dims, N, R, dt, (char *)workspace, 0);
-    int nwant = 0;
-    bool want_left = false, want_right = false;
-    TreePlan tree = plan_tree(dims, N, R);
-    for (int n = 0; n < N; ++n)
-        if (outs[n]) {
-            ++nwant;
-            (n < tree.s ? want_left : want_right) = true;
-        }
-    tree.use = tree.use && nwant >= 3 && tree_reach_ok(tree, X, R, dt);
-    if (tree.use) {
-        if (want_left) {
-            s = tree_pass(tree, true, X, factors, R, dt, w, stream);
-            if (s) return s;
-        }
-        if (want_right) {
-            s = tree_pass(tree, false, X, factors, R, dt, w, stream);
-            if (s) return s;
-        }
+    return all_enqueue(X, dims, N, factors, R, outs, dt, layout_all(dims, N, R, dt, (char *)workspace, 0), stream);
+}
+
+size_t cpm_sympair_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {
+    std::string saved = g_last_error;
+    if (check_sym(dims, N, R, dt)) {
+        g_last_error = saved;
+        return 0;
     }
-    for (int n = 0; n < N; ++n) {
-        if (!outs[n]) continue;
-        if (tree.use) {
-            s = tree_leaf(tree, dims, N, factors, R, n, dt, w, outs[n], stream);
-        } else {
-            const Plan p = make_plan(dims, N, R, n, dt, X);
-            s = run_mttkrp(p, X, dims, N, factors, R, n, outs[n], dt, w.mws, stream);
-        }
-        if (s) return s;
+    return layout_sym(sym_view(dims, N), R, dt, nullptr).need;
+}
+
+cpm_status mttkrp_sympair(const void *Xp, const int64_t *dims, int N, const void *const *factors, int R,
+                          void *const *outs, cpm_dtype dt, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    cpm_status s = check_sym(dims, N, R, dt);
+    if (s) return s;
+    if (!Xp) return fail(CPM_EINVAL, "Xp is null");
+    if (!factors) return fail(CPM_EINVAL, "factors is null");
+    if (!outs) return fail(CPM_EINVAL, "outs is null");
+    for (int k = 0; k < N; ++k)
+        if (!factors[k]) return fail(CPM_EINVAL, "factors[%d] is null", k);
+    s = check_factor_reach(dims, N, R, dt, -1);
+    if (s) return s;
+    const SymView v = sym_view(dims, N);
+    s = check_factor_reach(v.vd, 1, R, dt, -1);  // the pair factor W
+    if (s) return s;
+    const size_t need = layout_sym(v, R, dt, nullptr).need;
+    if (!workspace || ws_bytes < need)
+        return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    s = check_reach(Xp, v.vd, v.NV, R, dt);
+    if (s) return s;
+    const SymWs w = layout_sym(v, R, dt, (char *)workspace);
+    const bool want_pair = outs[0] || outs[1];
+    bool want_rest = false;
+    for (int k = 2; k < N; ++k) want_rest = want_rest || outs[k];
+    if (!want_pair && !want_rest) return CPM_OK;
+    const size_t fz = dtype_f_bytes(dt);
+    if (want_rest) {
+        const unsigned blocks = (unsigned)std::min<int64_t>(4096, ceil_div(v.P * R, kThreads));
+        if (fz == 8)
+            hipLaunchKernelGGL(k_sympair_rows<double>, dim3(blocks), dim3(kThreads), 0, stream,
+                               (const double *)factors[0], (const double *)factors[1], v.P, R, (double *)w.W);
+        else
+            hipLaunchKernelGGL(k_sympair_rows<float>, dim3(blocks), dim3(kThreads), 0, stream,
+                               (const float *)factors[0], (const float *)factors[1], v.P, R, (float *)w.W);
+        LAUNCH_CHECK("k_sympair_rows");
     }
+    // the view: factors (W, U_2, ...), outputs (T, M_2, ...)
+    const void *vf[CPM_MAX_MODES];
+    void *vo[CPM_MAX_MODES];
+    vf[0] = want_rest ? w.W : nullptr;
+    vo[0] = want_pair ? w.T : nullptr;
+    for (int k = 2; k < N; ++k) {
+        vf[k - 1] = factors[k];
+        vo[k - 1] = outs[k];
+    }
+    s = all_enqueue(Xp, v.vd, v.NV, vf, R, vo, dt, w.all, stream);
+    if (s) return s;
+    for (int m = 0; m < 2; ++m) {
+        if (!outs[m]) continue;
+        const dim3 grid((unsigned)v.n, (unsigned)ceil_div(R, 64));
+        const void *other = factors[1 - m];
+        if (fz == 8)
+            hipLaunchKernelGGL(k_sympair_leaf<double>, grid, dim3(kThreads), 0, stream, (const double *)w.T,
+                               (const double *)other, v.n, R, (double *)outs[m]);
+        else
+            hipLaunchKernelGGL(k_sympair_leaf<float>, grid, dim3(kThreads), 0, stream, (const float *)w.T,
+                               (const float *)other, v.n, R, (float *)outs[m]);
+        LAUNCH_CHECK("k_sympair_leaf");
+    }
+    return CPM_OK;
+}
+
+cpm_status cpm_pack_sympair(const void *X, const int64_t *dims, int N, cpm_dtype dt, void *Xp, hipStream_t stream) {
+    cpm_status s = check_sym(dims, N, 1, dt);
+    if (s) return s;
+    if (!X || !Xp) return fail(CPM_EINVAL, "X or Xp is null");
+    const SymView v = sym_view(dims, N);
+    const dim3 grid((unsigned)ceil_div(v.P, kThreads), (unsigned)std::min<int64_t>(v.rest, 1024),
+                    dt == CPM_BF16X2 ? 2u : 1u);
+    if (dt == CPM_F64)
+        hipLaunchKernelGGL(k_pack_sympair<uint64_t>, grid, dim3(kThreads), 0, stream, (const uint64_t *)X, v.n,
+                           v.rest, (uint64_t *)Xp);
+    else if (dt == CPM_F32)
+        hipLaunchKernelGGL(k_pack_sympair<uint32_t>, grid, dim3(kThreads), 0, stream, (const uint32_t *)X, v.n,
+                           v.rest, (uint32_t *)Xp);
+    else
+        hipLaunchKernelGGL(k_pack_sympair<uint16_t>, grid, dim3(kThreads), 0, stream, (const uint16_t *)X, v.n,
+                           v.rest, (uint16_t *)Xp);
+    LAUNCH_CHECK("k_pack_sympair");
     return CPM_OK;
 }
 

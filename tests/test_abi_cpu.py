@@ -238,3 +238,23 @@ def test_mttkrp_all_with_no_requested_mode_is_a_no_op():
     need = _abi.mttkrp_all_workspace_bytes(d, 32, _abi.CPM_F32)
     nulls = (ctypes.c_void_p * 5)(*([None] * 5))
     assert call_mttkrp_all(d, R=32, outs=nulls, ws=FAKE, ws_len=need) == _abi.CPM_OK
+
+
+def test_sympair_validates_before_launch():
+    lib = _abi.load()
+    d = _dims((6, 6, 5))
+    f, o = _ptrs(3), _ptrs(3)
+    assert lib.mttkrp_sympair(FAKE, _dims((6, 7, 5)), 3, f, 4, o, 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.mttkrp_sympair(FAKE, _dims((6, 6)), 2, _ptrs(2), 4, _ptrs(2), 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.mttkrp_sympair(None, d, 3, f, 4, o, 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.mttkrp_sympair(FAKE, d, 3, _ptrs(3, null_at=0), 4, o, 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.mttkrp_sympair(FAKE, d, 3, f, 4, None, 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.mttkrp_sympair(FAKE, d, 3, f, 257, o, 0, FAKE, 1 << 30, None) == _abi.CPM_EUNSUPPORTED
+    assert lib.mttkrp_sympair(FAKE, d, 3, f, 4, o, 0, FAKE, 16, None) == _abi.CPM_EWORKSPACE
+    assert lib.cpm_pack_sympair(FAKE, _dims((6, 7, 5)), 3, 0, FAKE, None) == _abi.CPM_EINVAL
+    assert lib.cpm_pack_sympair(None, d, 3, 0, FAKE, None) == _abi.CPM_EINVAL
+    # the workspace holds the pair factor and the pair intermediate (P x R each)
+    P = 256 * 257 // 2
+    ws = _abi.sympair_workspace_bytes((256, 256, 512, 32), 64, _abi.CPM_F32)
+    assert ws >= 2 * P * 64 * 4
+    assert _abi.sympair_workspace_bytes((6, 7, 5), 4, _abi.CPM_F32) == 0
