@@ -168,6 +168,29 @@ cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *con
                       hipStream_t stream);
 
 /*
+ * The straightforward MTTKRP the paper measures against (Section 2.3; its
+ * Section 5.3 also times one matrix multiplication of the same shape as a
+ * lower bound): X_(n) formed explicitly by reordering the entries (internal
+ * modes; X_(0) and X_(N-1) are already column- and row-major matrices in
+ * the natural layout, as the paper notes, and are used in place), the full
+ * Khatri-Rao product U_{N-1} kr ... kr U_{n+1} kr U_{n-1} kr ... kr U_0
+ * formed explicitly (I / I_n rows of R values), then one hipBLASLt GEMM
+ * M = X_(n) K.  Provided to measure the fused kernels against it; it moves
+ * the tensor up to three times (read, reordered copy written and read) plus
+ * the Khatri-Rao product.  Arguments as for `mttkrp`; CPM_F32 or CPM_F64
+ * (CPM_BF16X2 gives CPM_EUNSUPPORTED).  The workspace holds the reordered
+ * tensor (internal modes), the Khatri-Rao product and 32 MiB for the GEMM.
+ * The first call on a device creates a hipBLASLt handle (which allocates);
+ * the algorithm for each GEMM shape is chosen once and kept.  A shape for
+ * which hipBLASLt offers no algorithm (float64 with R = 1 or I_n = 1 on
+ * gfx950) gives CPM_EUNSUPPORTED; the reordering and the Khatri-Rao product
+ * have then been enqueued into the workspace but nothing is written to out.
+ */
+size_t cpm_explicit_workspace_bytes(const int64_t *dims, int N, int R, int mode, cpm_dtype dt);
+cpm_status mttkrp_explicit(const void *X, const int64_t *dims, int N, const void *const *factors, int R, int mode,
+                           void *out, cpm_dtype dt, void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Symmetric-pair packed storage (Section 5.3.3 stores the symmetric
  * region-by-region pair of its fMRI tensor as one linearised triangle).
  * A tensor with I_0 = I_1 = n and X(i, j, rest) = X(j, i, rest) is held as

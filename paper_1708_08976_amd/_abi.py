@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_EUNSUPPORTED", 3: "CPM_ENO
 
 EXPORTS = ["cpm_version", "cpm_last_error", "cpm_mttkrp_workspace_bytes", "mttkrp", "mttkrp_scratch",
            "cpm_mttkrp_describe", "cpm_mttkrp_all_workspace_bytes", "mttkrp_all",
-           "cpm_sympair_workspace_bytes", "mttkrp_sympair", "cpm_pack_sympair",
+           "cpm_explicit_workspace_bytes", "mttkrp_explicit", "cpm_sympair_workspace_bytes", "mttkrp_sympair", "cpm_pack_sympair",
            "cpm_residual2_workspace_bytes", "cpm_residual2",
            "cpm_cp_als_workspace_bytes", "cpm_cp_grad_workspace_bytes", "cp_als_step", "cp_grad",
            "cpm_xnorm2_workspace_bytes", "cpm_xnorm2", "cpm_split_bf16", "cpm_krp_rows"]
@@ -60,6 +60,10 @@ def load():
     lib.cpm_mttkrp_all_workspace_bytes.restype = sz
     lib.mttkrp_all.argtypes = [vp, i64p, ci, vpp, ci, vpp, ci, vp, sz, vp]
     lib.mttkrp_all.restype = ci
+    lib.cpm_explicit_workspace_bytes.argtypes = [i64p, ci, ci, ci, ci]
+    lib.cpm_explicit_workspace_bytes.restype = sz
+    lib.mttkrp_explicit.argtypes = [vp, i64p, ci, vpp, ci, ci, vp, ci, vp, sz, vp]
+    lib.mttkrp_explicit.restype = ci
     lib.cpm_sympair_workspace_bytes.argtypes = [i64p, ci, ci, ci]
     lib.cpm_sympair_workspace_bytes.restype = sz
     lib.mttkrp_sympair.argtypes = [vp, i64p, ci, vpp, ci, vpp, ci, vp, sz, vp]
@@ -220,6 +224,34 @@ def mttkrp_all(X, dims, factors, outs=None, modes=None, dtype=None, workspace=No
                           0 if workspace is None else workspace.numel() * workspace.element_size(),
                           _stream(X.device, stream)))
     return outs
+
+
+def explicit_workspace_bytes(dims, R, mode, dtype):
+    return load().cpm_explicit_workspace_bytes(_dims(dims), len(dims), int(R), int(mode), int(dtype))
+
+
+def mttkrp_explicit(X, dims, factors, mode, out=None, dtype=None, workspace=None, stream=None):
+    """The straightforward MTTKRP (explicit X_(n), explicit Khatri-Rao
+    product, one GEMM) -> out (I_mode x R)."""
+    lib = load()
+    dt = _dtype_code(X, dtype)
+    _require(X, "X")
+    R = int(next(f for f in factors if f is not None).shape[1])
+    fdt = torch.float64 if dt == CPM_F64 else torch.float32
+    for k, f in enumerate(factors):
+        if f is not None and k != mode:
+            _require(f, "factors[%d]" % k)
+    if out is None:
+        out = torch.empty((int(dims[mode]), R), dtype=fdt, device=X.device)
+    _require(out, "out")
+    need = lib.cpm_explicit_workspace_bytes(_dims(dims), len(dims), R, int(mode), dt)
+    if workspace is None:
+        workspace = _workspace(need, X.device)
+    _check(lib.mttkrp_explicit(X.data_ptr(), _dims(dims), len(dims), _ptrs(factors), R, int(mode), out.data_ptr(),
+                               dt, None if workspace is None else workspace.data_ptr(),
+                               0 if workspace is None else workspace.numel() * workspace.element_size(),
+                               _stream(X.device, stream)))
+    return out
 
 
 def sympair_workspace_bytes(dims, R, dtype):

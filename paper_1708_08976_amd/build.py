@@ -14,6 +14,8 @@ FLAGS = [
     # hipcc -O3 may emit packed float32 arithmetic on its own; keep it off.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # the explicit baseline's GEMM
+    "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lhipblaslt",
 ]
 
 

@@ -1,8 +1,11 @@
 // C-ABI of the cpmttkrp library: argument validation, launch planning and
 // the entry points declared in include/cpmttkrp.h.
 #include <hip/hip_runtime.h>
+#include <hipblaslt/hipblaslt.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -13,6 +16,7 @@
 #include "../../include/cpmttkrp.h"
 #include "als_kernels.hpp"
 #include "bf16_kernels.hpp"
+#include "explicit_kernels.hpp"
 #include "mttkrp32_kernels.hpp"
 #include "mttkrp_kernels.hpp"
 #include "residual_kernels.hpp"
@@ -212,8 +216,7 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
 }
 
 // Float32 tiling on the 32x32 MFMA kernels (mttkrp32_kernels.hpp).
-// Left-first once the left product has 32 entries (and rows allow 16-byte
-// loads); right-first otherwise.  The inner part of the contracted index
+// Left-first once the left product has 32 entries; right-first otherwise.  The inner part of the contracted index
 // is grown until it reaches the chunk length (a long inner range is then cut
 // into chunks).  Returns false when these kernels do not apply.
 constexpr int64_t kF32Chunk = 128;  // inner entries per work-group (tile of 16 KB per 32 columns)
@@ -243,7 +246,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         } else {
             while (q < mode && p.G_in < kF32Chunk) p.G_in *= dims[q++];
         }
-        if (p.G_in % 4 != 0 || xa % 16 != 0) return false;  // rows need 16-byte loads
+        if (xa % 4 != 0) return false;  // rows need 4-byte alignment
         p.p = q;
         p.G_out = p.IL / p.G_in;
         p.n_outer = p.G_out * p.IR;
@@ -261,6 +264,11 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
     } else {
         p.kind = kRight32;
         p.J = p.In * p.IL;
+        if (xa % 4 != 0) return false;
+        // Any row length works (a lane whose entries straddle J loads them
+        // one by one), but unaligned rows measured slower at TJ = 4 (mode 0
+        // of 225 x 59 x 200 x 200: 0.88 ms against 0.65 ms at TJ = 1), so
+        // the wide forms are kept for rows of aligned length.
         const bool a4 = p.J % 4 == 0 && xa % 16 == 0, a2 = p.J % 2 == 0 && xa % 8 == 0;
         // Waves split the rows of a narrow j tile: the partial result of a
         // work-group (its j tile x R) stays small next to the X it streams.
@@ -1038,6 +1046,121 @@ cpm_status check_sym(const int64_t *dims, int N, int R, cpm_dtype dt) {
     return CPM_OK;
 }
 
+// ------------------ the straightforward baseline (Section 2.3) --------------
+// X_(n) reordered explicitly (internal modes), the full Khatri-Rao product
+// formed explicitly, one hipBLASLt matrix multiplication.
+constexpr size_t kGemmWsBytes = (size_t)32 << 20;
+constexpr int kMaxDevicesBlas = 64;
+
+struct ExplicitWs {
+    void *Y, *K, *gemm;
+    size_t need;
+};
+
+ExplicitWs layout_explicit(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, char *base) {
+    ExplicitWs w{};
+    int64_t I = 1;
+    for (int k = 0; k < N; ++k) I *= dims[k];
+    const size_t fz = dtype_f_bytes(dt);
+    const bool internal = mode > 0 && mode < N - 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    w.Y = internal ? take((size_t)I * fz) : nullptr;
+    w.K = take((size_t)(I / dims[mode]) * R * fz);
+    w.gemm = take(kGemmWsBytes);
+    w.need = off;
+    return w;
+}
+
+// hipBLASLt handle per device, created on first use with that device
+// current, and the algorithm chosen for each GEMM shape.
+std::mutex g_blas_mu;
+hipblasLtHandle_t g_blas[kMaxDevicesBlas];
+std::map<std::tuple<int, int, int, int64_t, int64_t, int>, hipblasLtMatmulAlgo_t> g_algo;
+
+cpm_status blas_handle(int dev, hipblasLtHandle_t *h) {
+    if (dev < 0 || dev >= kMaxDevicesBlas) return fail(CPM_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevicesBlas);
+    if (!g_blas[dev]) {
+        hipblasLtHandle_t nh = nullptr;
+        if (hipblasLtCreate(&nh) != HIPBLAS_STATUS_SUCCESS || !nh) return fail(CPM_EHIP, "hipblasLtCreate failed");
+        g_blas[dev] = nh;
+    }
+    *h = g_blas[dev];
+    return CPM_OK;
+}
+
+// D (R x In, column-major, ld R: M row-major) = K^T (R x J, ld R) * op(B):
+// rowmajor = false: B is X_(n) column-major (In x J, ld In), op = transpose;
+// rowmajor = true: B is X_(n) row-major, i.e. (J x In, ld J), op = none.
+cpm_status gemm_mttkrp(const void *K, const void *B, bool rowmajor, int64_t In, int64_t J, int R, cpm_dtype dt,
+                       void *out, void *gws, hipStream_t st) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const hipDataType ty = dt == CPM_F64 ? HIP_R_64F : HIP_R_32F;
+    const hipblasComputeType_t ct = dt == CPM_F64 ? HIPBLAS_COMPUTE_64F : HIPBLAS_COMPUTE_32F;
+    std::lock_guard<std::mutex> lock(g_blas_mu);
+    hipblasLtHandle_t h;
+    cpm_status s = blas_handle(dev, &h);
+    if (s) return s;
+    hipblasLtMatmulDesc_t op = nullptr;
+    hipblasLtMatrixLayout_t la = nullptr, lb = nullptr, lc = nullptr;
+    hipblasLtMatmulPreference_t pref = nullptr;
+    auto cleanup = [&]() {
+        if (pref) hipblasLtMatmulPreferenceDestroy(pref);
+        if (lc) hipblasLtMatrixLayoutDestroy(lc);
+        if (lb) hipblasLtMatrixLayoutDestroy(lb);
+        if (la) hipblasLtMatrixLayoutDestroy(la);
+        if (op) hipblasLtMatmulDescDestroy(op);
+    };
+    const hipblasOperation_t ta = HIPBLAS_OP_N, tb = rowmajor ? HIPBLAS_OP_N : HIPBLAS_OP_T;
+    bool ok = hipblasLtMatmulDescCreate(&op, ct, ty) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulDescSetAttribute(op, HIPBLASLT_MATMUL_DESC_TRANSA, &ta, sizeof(ta)) ==
+                  HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulDescSetAttribute(op, HIPBLASLT_MATMUL_DESC_TRANSB, &tb, sizeof(tb)) ==
+                  HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatrixLayoutCreate(&la, ty, (uint64_t)R, (uint64_t)J, R) == HIPBLAS_STATUS_SUCCESS &&
+              (rowmajor ? hipblasLtMatrixLayoutCreate(&lb, ty, (uint64_t)J, (uint64_t)In, J)
+                        : hipblasLtMatrixLayoutCreate(&lb, ty, (uint64_t)In, (uint64_t)J, In)) ==
+                  HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatrixLayoutCreate(&lc, ty, (uint64_t)R, (uint64_t)In, R) == HIPBLAS_STATUS_SUCCESS;
+    if (!ok) {
+        cleanup();
+        return fail(CPM_EHIP, "hipBLASLt descriptor set-up failed");
+    }
+    const auto key = std::make_tuple(dev, (int)dt, R, In, J, (int)rowmajor);
+    auto it = g_algo.find(key);
+    if (it == g_algo.end()) {
+        const uint64_t wsb = kGemmWsBytes;
+        hipblasLtMatmulHeuristicResult_t res[1];
+        int count = 0;
+        ok = hipblasLtMatmulPreferenceCreate(&pref) == HIPBLAS_STATUS_SUCCESS &&
+             hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wsb,
+                                                   sizeof(wsb)) == HIPBLAS_STATUS_SUCCESS &&
+             hipblasLtMatmulAlgoGetHeuristic(h, op, la, lb, lc, lc, pref, 1, res, &count) ==
+                 HIPBLAS_STATUS_SUCCESS &&
+             count > 0;
+        if (!ok) {
+            cleanup();
+            return fail(CPM_EUNSUPPORTED, "hipBLASLt has no algorithm for this %s GEMM (%d x %lld x %lld)",
+                        dt == CPM_F64 ? "float64" : "float32", R, (long long)In, (long long)J);
+        }
+        it = g_algo.emplace(key, res[0].algo).first;
+    }
+    const double a64 = 1.0, b64 = 0.0;
+    const float a32 = 1.f, b32 = 0.f;
+    const void *alpha = dt == CPM_F64 ? (const void *)&a64 : (const void *)&a32;
+    const void *beta = dt == CPM_F64 ? (const void *)&b64 : (const void *)&b32;
+    const hipblasStatus_t bs =
+        hipblasLtMatmul(h, op, alpha, K, la, B, lb, beta, out, lc, out, lc, &it->second, gws, kGemmWsBytes, st);
+    cleanup();
+    if (bs != HIPBLAS_STATUS_SUCCESS) return fail(CPM_EHIP, "hipblasLtMatmul failed (status %d)", (int)bs);
+    return CPM_OK;
+}
+
 // ------------------------------ residual ------------------------------------
 // X viewed as Rr rows (modes s..N-1) of L contiguous entries (modes 0..s-1);
 // s maximises the used part of a work-group's 128 x 32 output tile,
@@ -1506,6 +1629,68 @@ cpm_status cpm_pack_sympair(const void *X, const int64_t *dims, int N, cpm_dtype
                            v.rest, (uint16_t *)Xp);
     LAUNCH_CHECK("k_pack_sympair");
     return CPM_OK;
+}
+
+size_t cpm_explicit_workspace_bytes(const int64_t *dims, int N, int R, int mode, cpm_dtype dt) {
+    int64_t total;
+    std::string saved = g_last_error;
+    if (check_dtype(dt) || dt == CPM_BF16X2 || check_shape(dims, N, R, &total, CPM_MAX_RANK) || mode < 0 ||
+        mode >= N) {
+        g_last_error = saved;
+        return 0;
+    }
+    return layout_explicit(dims, N, R, mode, dt, nullptr).need;
+}
+
+cpm_status mttkrp_explicit(const void *X, const int64_t *dims, int N, const void *const *factors, int R, int mode,
+                           void *out, cpm_dtype dt, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    int64_t total;
+    cpm_status s = validate_mttkrp(X, dims, N, factors, R, mode, out, dt, &total);
+    if (s) return s;
+    if (dt == CPM_BF16X2) return fail(CPM_EUNSUPPORTED, "mttkrp_explicit takes float32 or float64 tensors");
+    const size_t need = layout_explicit(dims, N, R, mode, dt, nullptr).need;
+    if (!workspace || ws_bytes < need)
+        return fail(CPM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    const ExplicitWs w = layout_explicit(dims, N, R, mode, dt, (char *)workspace);
+    int64_t IL = 1, IR = 1;
+    for (int k = 0; k < mode; ++k) IL *= dims[k];
+    for (int k = mode + 1; k < N; ++k) IR *= dims[k];
+    const int64_t In = dims[mode], J = IL * IR;
+    // 1. X_(n): reordered for internal modes; the tensor itself otherwise
+    const void *B = X;
+    const bool rowmajor = mode == N - 1 && N > 1;
+    if (w.Y) {
+        const int64_t tiles = ceil_div(IL, 64) * ceil_div(In, 64) * IR;
+        const unsigned blocks = (unsigned)std::min<int64_t>(tiles, 65536);
+        if (dt == CPM_F64)
+            hipLaunchKernelGGL(k_unfold<uint64_t>, dim3(blocks), dim3(kThreads), 0, stream, (const uint64_t *)X, IL,
+                               In, IR, (uint64_t *)w.Y);
+        else
+            hipLaunchKernelGGL(k_unfold<uint32_t>, dim3(blocks), dim3(kThreads), 0, stream, (const uint32_t *)X, IL,
+                               In, IR, (uint32_t *)w.Y);
+        LAUNCH_CHECK("k_unfold");
+        B = w.Y;
+    }
+    // 2. the full Khatri-Rao product, rows in the natural order of the other
+    // modes (mode 0 fastest): U_{N-1} kr ... kr U_{n+1} kr U_{n-1} kr ... kr U_0
+    int om[CPM_MAX_MODES];
+    int no = 0;
+    for (int k = 0; k < N; ++k)
+        if (k != mode) om[no++] = k;
+    const int RP = (R + 15) / 16 * 16;
+    const unsigned kblocks = (unsigned)ceil_div(J, 64);
+    if (dt == CPM_F64) {
+        const Krp<double> k = krp_of<double>(factors, dims, om, no);
+        hipLaunchKernelGGL(k_krp_rows<double>, dim3(kblocks), dim3(kThreads), 0, stream, k, R, RP, (int64_t)0, J,
+                           (double *)w.K);
+    } else {
+        const Krp<float> k = krp_of<float>(factors, dims, om, no);
+        hipLaunchKernelGGL(k_krp_rows<float>, dim3(kblocks), dim3(kThreads), 0, stream, k, R, RP, (int64_t)0, J,
+                           (float *)w.K);
+    }
+    LAUNCH_CHECK("k_krp_rows");
+    // 3. one GEMM
+    return gemm_mttkrp(w.K, B, rowmajor, In, J, R, dt, out, w.gemm, stream);
 }
 
 size_t cpm_residual2_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype dt) {

@@ -13,7 +13,9 @@
 //   * X arrives in 16-byte buffer loads, eight lanes per 128-byte row
 //     segment (left-first, staged through LDS into MFMA layout) or 512
 //     contiguous bytes per row (right-first), with a ring of RING register
-//     sets so RING - 1 steps are in flight;
+//     sets so RING - 1 steps are in flight; rows need only 4-byte
+//     alignment (row lengths need not be multiples of 4: the four entries
+//     that straddle a chunk or row end are loaded one by one);
 //   * the outer scale S(o, c) of the current block multiplies the B
 //     operands as they leave LDS, so the MFMA accumulates full Khatri-Rao
 //     values K_in(g, c) * S(o, c) directly: one accumulator set, no
@@ -73,7 +75,6 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
     const int64_t row_w = (int64_t)blockIdx.x * 32 * WM + 32 * wm;  // first row of this wave
     const int64_t o_begin = split * blocks_per_split;
     const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
-    const bool has_out = kout.Z > 0;
     const int wl = wc * WS * SPB;  // wave's first entry within the chunk
     float *stg = tile + RP * PT + wave * 32 * WS;  // this wave's staging slot [32 rows][32 entries]
 
@@ -98,9 +99,17 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
         const int e0 = wl + WS * ls + 4 * ch;  // chunk-relative entry of this lane
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            uint32_t off = loff[i] + (uint32_t)(WS * ls * 4);
-            if (ragged) off = e0 < lcount ? off : kNoLoad;
-            a[i] = buf_load4(rs, off, 0.f);
+            const uint32_t off = loff[i] + (uint32_t)(WS * ls * 4);
+            if (!ragged || e0 + 4 <= lcount) {
+                a[i] = buf_load4(rs, off, 0.f);
+            } else {
+                // the chunk ends inside (or before) this lane's four entries
+                // (inner ranges that are not a multiple of 4): single loads
+                // of the entries inside it, zeros for the rest, so no load
+                // reaches past the chunk
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[i][t] = buf_load1(rs, e0 + t < lcount ? off + 4 * t : kNoLoad, 0.f);
+            }
         }
         if (++ls == SPB) {
             ls = 0;
@@ -259,7 +268,6 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
     const int64_t jw = (int64_t)blockIdx.x * JW * WJ + JW * wj;  // first j of this wave
     const int64_t o_begin = split * blocks_per_split;
     const int64_t o_end = min(n_outer, o_begin + blocks_per_split);
-    const bool has_out = kout.Z > 0;
     const int wrow = wr * 8 * SPB;  // wave's first row within the chunk
     const bool jok = jw + TJ * m < J;
     const bool wave_live = jw < J;
@@ -280,13 +288,27 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
     uint32_t loff[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) loff[s] = (uint32_t)(((int64_t)(4 * h + s) * J + TJ * m) * 4);
+    // a lane whose TJ entries cross the row end J (J not a multiple of TJ)
+    const bool jpart = jok && jw + TJ * m + TJ > J;
     int ls = 0;
     auto load_step = [&](jv (&a)[4]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            uint32_t off = loff[s] + (uint32_t)(8 * ls * J * 4);
-            if (jragged) off = jok ? off : kNoLoad;
-            a[s] = buf_loadj<TJ>(rs, off);
+            const uint32_t off = loff[s] + (uint32_t)(8 * ls * J * 4);
+            if (!jragged) {
+                a[s] = buf_loadj<TJ>(rs, off);
+            } else if (!jpart) {
+                a[s] = buf_loadj<TJ>(rs, jok ? off : kNoLoad);
+            } else {
+                // single loads of the entries before J, zeros past it
+                if constexpr (TJ == 1) {
+                    a[s] = buf_load1(rs, off, 0.f);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TJ; ++t)
+                        a[s][t] = buf_load1(rs, jw + TJ * m + t < J ? off + 4 * t : kNoLoad, 0.f);
+                }
+            }
         }
         if (++ls == SPB) {
             ls = 0;

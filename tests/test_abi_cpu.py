@@ -162,8 +162,12 @@ def test_describe_names_the_kernel_and_launch():
     assert _abi.describe((512, 512, 512), 32, 0, _abi.CPM_F32).startswith("k_right32<")
     assert _abi.describe((60, 50, 40), 8, 0, _abi.CPM_F64).startswith("k_contract_right<f64")
     assert _abi.describe((256, 256, 512, 32), 128, 0, _abi.CPM_BF16X2).startswith("k_contract_right_bf16<NB=8")
-    # rows not 16-byte aligned: the 16x16 float kernels
-    assert _abi.describe((60, 50, 40), 8, 1, _abi.CPM_F32, X=4100).startswith("k_contract_left<f32")
+    # rows need only 4-byte alignment on the 32x32 kernels
+    assert _abi.describe((60, 50, 40), 8, 1, _abi.CPM_F32, X=4100).startswith("k_left32<")
+    assert _abi.describe((165, 165, 165, 165), 25, 2, _abi.CPM_F32).startswith("k_left32<")
+    assert _abi.describe((165, 165, 165, 165), 25, 0, _abi.CPM_F32).startswith("k_right32<NC=1,TJ=1")
+    # rows 31 * IL apart beyond one buffer resource: the 16x16 float kernels
+    assert _abi.describe((40000000, 2, 2), 8, 1, _abi.CPM_F32).startswith("k_contract_left<f32")
     lib = _abi.load()
     buf = ctypes.create_string_buffer(8)
     assert lib.cpm_mttkrp_describe(_dims((4, 5, 6)), 3, 8, 3, 0, 4096, buf, 8) == _abi.CPM_EINVAL
@@ -258,3 +262,18 @@ def test_sympair_validates_before_launch():
     ws = _abi.sympair_workspace_bytes((256, 256, 512, 32), 64, _abi.CPM_F32)
     assert ws >= 2 * P * 64 * 4
     assert _abi.sympair_workspace_bytes((6, 7, 5), 4, _abi.CPM_F32) == 0
+
+
+def test_explicit_validates_before_launch():
+    lib = _abi.load()
+    d = _dims((6, 7, 5))
+    f = _ptrs(3)
+    assert lib.mttkrp_explicit(FAKE, d, 3, f, 4, 1, FAKE, 2, FAKE, 1 << 30, None) == _abi.CPM_EUNSUPPORTED
+    assert lib.mttkrp_explicit(None, d, 3, f, 4, 1, FAKE, 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.mttkrp_explicit(FAKE, d, 3, f, 4, 3, FAKE, 0, FAKE, 1 << 30, None) == _abi.CPM_EINVAL
+    assert lib.mttkrp_explicit(FAKE, d, 3, f, 4, 1, FAKE, 0, FAKE, 16, None) == _abi.CPM_EWORKSPACE
+    # internal modes hold the reordered tensor; external ones do not
+    ws1 = _abi.explicit_workspace_bytes((512, 512, 512), 32, 1, _abi.CPM_F32)
+    ws0 = _abi.explicit_workspace_bytes((512, 512, 512), 32, 0, _abi.CPM_F32)
+    assert ws1 - ws0 >= 512 ** 3 * 4
+    assert _abi.explicit_workspace_bytes((512, 512, 512), 32, 0, _abi.CPM_BF16X2) == 0
