@@ -23,6 +23,8 @@
 //     table (fill_scales), so reading them never waits behind X loads.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace cpm {
@@ -95,18 +97,22 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
 #pragma unroll
     for (int i = 0; i < 4; ++i) loff[i] = (uint32_t)(((int64_t)(8 * i + (lane >> 3)) * IL + wl + 4 * ch) * 4);
     int ls = 0;
-    auto load_step = [&](f32x4 (&a)[4]) {
+    // One step's loads.  PART (a chunk that ends inside a group of four
+    // entries, for inner ranges that are not a multiple of 4) takes single
+    // loads of the entries inside the chunk and zeros for the rest, so no
+    // load reaches past it.  The two forms are separate copies of the
+    // stream below, each with a fixed number of loads per step, so the
+    // waits before a step's data is used count only that step's loads and
+    // RING - 1 steps stay in flight.
+    auto load_step = [&](auto part_c, f32x4 (&a)[4]) {
+        constexpr bool PART = decltype(part_c)::value;
         const int e0 = wl + WS * ls + 4 * ch;  // chunk-relative entry of this lane
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t off = loff[i] + (uint32_t)(WS * ls * 4);
-            if (!ragged || e0 + 4 <= lcount) {
-                a[i] = buf_load4(rs, off, 0.f);
+            if constexpr (!PART) {
+                a[i] = buf_load4(rs, (!ragged || e0 < lcount) ? off : kNoLoad, 0.f);
             } else {
-                // the chunk ends inside (or before) this lane's four entries
-                // (inner ranges that are not a multiple of 4): single loads
-                // of the entries inside it, zeros for the rest, so no load
-                // reaches past the chunk
 #pragma unroll
                 for (int t = 0; t < 4; ++t) a[i][t] = buf_load1(rs, e0 + t < lcount ? off + 4 * t : kNoLoad, 0.f);
             }
@@ -122,13 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
         }
     };
 
-    f32x4 x[RING][4];
-#pragma unroll
-    for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
-    build_tile_batched<float, RP, 16>(kin, R, c0, l0, LC, IL_in, [&](int q, int c, float v) { tile[c * PT + q] = v; });
-
     float *stab = stg + (4 - wave) * 32 * WS;  // [scale_blocks<RP>()][RP], after the four staging slots
-    fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
     int64_t co = o_begin, tb0 = o_begin;
     int cs = 0;
     float scl[NC];
@@ -167,29 +167,39 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
         }
     };
 
-    // Chunks of scale_blocks<RP>() blocks; within a chunk RING steps per pass with
-    // compile-time ring slots.
-    for (; tb0 < o_end; tb0 += scale_blocks<RP>()) {
-        if (tb0 != o_begin) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
-        __syncthreads();
-        co = tb0;
-        load_scales();
-        const int64_t nsteps = (min(o_end, tb0 + scale_blocks<RP>()) - tb0) * SPB;
-        int64_t st = 0;
-        for (; st + RING <= nsteps; st += RING) {
+    auto stream = [&](auto part_c) {
+        f32x4 x[RING][4];
 #pragma unroll
-            for (int k = 0; k < RING; ++k) {
-                load_step(x[(k + RING - 1) % RING]);
-                compute_step(x[k]);
+        for (int k = 0; k < RING - 1; ++k) load_step(part_c, x[k]);
+        build_tile_batched<float, RP, 16>(kin, R, c0, l0, LC, IL_in,
+                                          [&](int q, int c, float v) { tile[c * PT + q] = v; });
+        fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
+        // Chunks of scale_blocks<RP>() blocks; within a chunk RING steps per
+        // pass with compile-time ring slots.
+        for (; tb0 < o_end; tb0 += scale_blocks<RP>()) {
+            if (tb0 != o_begin) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
+            __syncthreads();
+            co = tb0;
+            load_scales();
+            const int64_t nsteps = (min(o_end, tb0 + scale_blocks<RP>()) - tb0) * SPB;
+            int64_t st = 0;
+            for (; st + RING <= nsteps; st += RING) {
+#pragma unroll
+                for (int k = 0; k < RING; ++k) {
+                    load_step(part_c, x[(k + RING - 1) % RING]);
+                    compute_step(x[k]);
+                }
             }
-        }
-        // only the last chunk can end off a RING boundary; its remaining
-        // steps are already in slots 0 .. RING - 2
+            // only the last chunk can end off a RING boundary; its remaining
+            // steps are already in slots 0 .. RING - 2
 #pragma unroll
-        for (int k = 0; k < RING - 1; ++k)
-            if (st + k < nsteps) compute_step(x[k]);
-        __syncthreads();  // every wave is done with this chunk's scales
-    }
+            for (int k = 0; k < RING - 1; ++k)
+                if (st + k < nsteps) compute_step(x[k]);
+            __syncthreads();  // every wave is done with this chunk's scales
+        }
+    };
+    if (ragged && (lcount & 3) != 0) stream(std::true_type{});
+    else stream(std::false_type{});
 
     // Sum the WC waves that share rows, in wave order, and store.
     __syncthreads();
@@ -241,6 +251,11 @@ __device__ inline float jcomp(const typename JVec<TJ>::type &v, int t) {
     if constexpr (TJ == 1) return v;
     else return v[t];
 }
+template <int TJ>
+__device__ inline void jset(typename JVec<TJ>::type &v, int t, float x) {
+    if constexpr (TJ == 1) v = x;
+    else v[t] = x;
+}
 
 template <int NC, int TJ, int WJ, int RING = 3>
 __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ X, int64_t J, int64_t IR_in,
@@ -288,26 +303,22 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
     uint32_t loff[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) loff[s] = (uint32_t)(((int64_t)(4 * h + s) * J + TJ * m) * 4);
-    // a lane whose TJ entries cross the row end J (J not a multiple of TJ)
-    const bool jpart = jok && jw + TJ * m + TJ > J;
     int ls = 0;
-    auto load_step = [&](jv (&a)[4]) {
+    // One step's loads.  PART (the last j tile of rows whose length J is not
+    // a multiple of TJ) loads entry by entry, zeros past J, so no lane's
+    // loads cross the row end; the two forms are separate copies of the
+    // stream below, each with a fixed number of loads per step.
+    auto load_step = [&](auto part_c, jv (&a)[4]) {
+        constexpr bool PART = decltype(part_c)::value;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const uint32_t off = loff[s] + (uint32_t)(8 * ls * J * 4);
-            if (!jragged) {
-                a[s] = buf_loadj<TJ>(rs, off);
-            } else if (!jpart) {
-                a[s] = buf_loadj<TJ>(rs, jok ? off : kNoLoad);
+            if constexpr (!PART || TJ == 1) {
+                a[s] = buf_loadj<TJ>(rs, (!jragged || jok) ? off : kNoLoad);
             } else {
-                // single loads of the entries before J, zeros past it
-                if constexpr (TJ == 1) {
-                    a[s] = buf_load1(rs, off, 0.f);
-                } else {
 #pragma unroll
-                    for (int t = 0; t < TJ; ++t)
-                        a[s][t] = buf_load1(rs, jw + TJ * m + t < J ? off + 4 * t : kNoLoad, 0.f);
-                }
+                for (int t = 0; t < TJ; ++t)
+                    jset<TJ>(a[s], t, buf_load1(rs, jw + TJ * m + t < J ? off + 4 * t : kNoLoad, 0.f));
             }
         }
         if (++ls == SPB) {
@@ -317,13 +328,7 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
         }
     };
 
-    jv x[RING][4];
-#pragma unroll
-    for (int k = 0; k < RING - 1; ++k) load_step(x[k]);
-    build_tile_batched<float, RP, 16>(kin, R, c0, r0, LC, IR_in, [&](int q, int c, float v) { tile[c * PT + q] = v; });
-
     float *stab = tile + RP * PT;  // [scale_blocks<RP>()][RP]
-    fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
     int64_t co = o_begin, tb0 = o_begin;
     int cs = 0;
     float scl[NC];
@@ -355,25 +360,35 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
         }
     };
 
-    for (; tb0 < o_end; tb0 += scale_blocks<RP>()) {
-        if (tb0 != o_begin) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
-        __syncthreads();
-        co = tb0;
-        load_scales();
-        const int64_t nsteps = (min(o_end, tb0 + scale_blocks<RP>()) - tb0) * SPB;
-        int64_t st = 0;
-        for (; st + RING <= nsteps; st += RING) {
+    auto stream = [&](auto part_c) {
+        jv x[RING][4];
 #pragma unroll
-            for (int k = 0; k < RING; ++k) {
-                load_step(x[(k + RING - 1) % RING]);
-                compute_step(x[k]);
+        for (int k = 0; k < RING - 1; ++k) load_step(part_c, x[k]);
+        build_tile_batched<float, RP, 16>(kin, R, c0, r0, LC, IR_in,
+                                          [&](int q, int c, float v) { tile[c * PT + q] = v; });
+        fill_scales<RP>(kout, R, c0, o_begin, o_end, stab);
+        for (; tb0 < o_end; tb0 += scale_blocks<RP>()) {
+            if (tb0 != o_begin) fill_scales<RP>(kout, R, c0, tb0, o_end, stab);
+            __syncthreads();
+            co = tb0;
+            load_scales();
+            const int64_t nsteps = (min(o_end, tb0 + scale_blocks<RP>()) - tb0) * SPB;
+            int64_t st = 0;
+            for (; st + RING <= nsteps; st += RING) {
+#pragma unroll
+                for (int k = 0; k < RING; ++k) {
+                    load_step(part_c, x[(k + RING - 1) % RING]);
+                    compute_step(x[k]);
+                }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < RING - 1; ++k)
-            if (st + k < nsteps) compute_step(x[k]);
-        __syncthreads();
-    }
+            for (int k = 0; k < RING - 1; ++k)
+                if (st + k < nsteps) compute_step(x[k]);
+            __syncthreads();
+        }
+    };
+    if (TJ > 1 && jragged && J % TJ != 0) stream(std::true_type{});
+    else stream(std::false_type{});
 
     auto store = [&](int64_t jrow, int c, float v) {
         if (jrow < J && c < R) partial[((int64_t)blockIdx.y * J + jrow) * R + c] = v;
