@@ -244,7 +244,10 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
             p.G_in = dims[q++];
             while (q < mode && p.G_in * dims[q] <= kF32Chunk) p.G_in *= dims[q++];
         } else {
-            while (q < mode && p.G_in < kF32Chunk) p.G_in *= dims[q++];
+            // a mode that would make the inner range more than 64 chunks long
+            // stays outer once the range holds one k-step group (32)
+            while (q < mode && p.G_in < kF32Chunk && !(p.G_in >= 32 && p.G_in * dims[q] > 64 * kF32Chunk))
+                p.G_in *= dims[q++];
         }
         if (xa % 4 != 0) return false;  // rows need 4-byte alignment
         p.p = q;
@@ -292,7 +295,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
             p.G_in = dims[q++];
             while (q < N && p.G_in * dims[q] <= lcap) p.G_in *= dims[q++];
         } else {
-            while (q < N && p.G_in < lcap) p.G_in *= dims[q++];
+            while (q < N && p.G_in < lcap && !(p.G_in >= 32 && p.G_in * dims[q] > 64 * lcap)) p.G_in *= dims[q++];
         }
         p.p = q;
         p.n_outer = p.IR / p.G_in;
