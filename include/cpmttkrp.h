@@ -77,7 +77,16 @@ typedef enum {
     CPM_EWORKSPACE = 5    /* workspace null or smaller than the queried size */
 } cpm_status;
 
-typedef enum { CPM_F32 = 0, CPM_F64 = 1, CPM_BF16X2 = 2 } cpm_dtype;
+/* The two range markers are not types: they make every int value a valid
+ * cpm_dtype object, so a caller's out-of-range code is well defined and is
+ * rejected with CPM_EINVAL. */
+typedef enum {
+    CPM_F32 = 0,
+    CPM_F64 = 1,
+    CPM_BF16X2 = 2,
+    CPM_DTYPE_RANGE_MIN_ = -2147483647 - 1,
+    CPM_DTYPE_RANGE_MAX_ = 2147483647
+} cpm_dtype;
 
 #define CPM_MAX_MODES 12
 #define CPM_MAX_RANK 256
