@@ -276,9 +276,17 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         // Waves split the rows of a narrow j tile: the partial result of a
         // work-group (its j tile x R) stays small next to the X it streams.
         int tj = 1;
-        const int wj = 1;
         if (p.NB == 1 && a4 && p.J >= 128) tj = 4;
         else if (a2 && p.J >= 64) tj = 2;
+        // A wide output (the cross-mode reuse's pass over a long left
+        // product): each wave takes its own j range and streams the whole
+        // contracted range, so the work-group needs no cross-wave reduction
+        // and writes its 4 x 32 x TJ outputs directly, while there are still
+        // enough j tiles to occupy every CU.
+        int wj = 1;
+        if (tight && ((p.NB == 1 && tj == 4) || (p.NB == 2 && tj == 2)) &&
+            ceil_div(p.J, 32 * tj * 4) >= kF32GroupsRight / 2)
+            wj = 4;
         p.Q = tj;
         p.MB = wj;
         const int64_t unit = 8 * (4 / wj);
@@ -529,6 +537,11 @@ void launch_right32_t(const Plan &p, const float *X, const Krp<float> &kin, cons
 
 void launch_right32(const Plan &p, const float *X, const Krp<float> &kin, const Krp<float> &kout, int R,
                     float *partial, hipStream_t st) {
+    if (p.MB == 4) {  // one j range per wave (wide outputs)
+        if (p.NB == 1) launch_right32_t<1, 4, 4>(p, X, kin, kout, R, partial, st);
+        else launch_right32_t<2, 2, 4>(p, X, kin, kout, R, partial, st);
+        return;
+    }
     if (p.NB == 1) {
         if (p.Q == 4) launch_right32_t<1, 4, 1>(p, X, kin, kout, R, partial, st);
         else if (p.Q == 2) launch_right32_t<1, 2, 1>(p, X, kin, kout, R, partial, st);
@@ -788,7 +801,30 @@ struct TreePlan {
 
 TreePlan plan_tree(const int64_t *dims, int N, int R) {
     TreePlan t{};
-    if (N < 4) return t;
+    if (N < 3) return t;
+    if (N == 3) {
+        // 3-way: modes 0 and 1 from one pass that contracts mode 2 (a
+        // right-first pass over the (I_0 I_1, I_2) view, whose wide output
+        // is the intermediate), mode 2 from an ordinary pass; taken only
+        // when that wide pass plans as one resident chunk per work-group
+        // (tree_reach_ok checks the launch)
+        // same entry count rule as below: the intermediates (written once,
+        // read by each leaf of their group) must move fewer entries than X
+        if (((double)dims[0] * dims[1] * 3 + (double)dims[2] * 2) * R > (double)dims[0] * dims[1] * dims[2])
+            return t;
+        t.use = true;
+        t.s = 2;
+        t.L = dims[0] * dims[1];
+        t.Rr = dims[2];
+        t.nA = 2;
+        t.dA[0] = t.L;
+        t.dA[1] = dims[2];
+        t.nB = 3;
+        t.dB[0] = dims[0];
+        t.dB[1] = dims[1];
+        t.dB[2] = dims[2];
+        return t;
+    }
     int64_t I = 1;
     for (int k = 0; k < N; ++k) I *= dims[k];
     double best = 0.0;
@@ -818,8 +854,13 @@ TreePlan plan_tree(const int64_t *dims, int N, int R) {
 }
 
 bool tree_reach_ok(const TreePlan &t, const void *X, int R, cpm_dtype dt) {
-    return make_plan(t.dA, t.nA, R, 0, dt, X).max_offset < kMaxBufferOffset &&
-           make_plan(t.dB, t.nB, R, t.s, dt, X).max_offset < kMaxBufferOffset;
+    const Plan a = make_plan(t.dA, t.nA, R, 0, dt, X);
+    if (t.nA == 2 && t.nB == 3) {
+        // the 3-way split: only the float32 wide pass with one j range per
+        // wave and the whole contracted mode resident is fast enough
+        if (!(a.kind == kRight32 && a.MB == 4 && a.nlc == 1)) return false;
+    }
+    return a.max_offset < kMaxBufferOffset && make_plan(t.dB, t.nB, R, t.s, dt, X).max_offset < kMaxBufferOffset;
 }
 
 // Leaf launch shape for mode t of a group with dims g[0..m).
@@ -882,7 +923,10 @@ AllWs layout_all(const int64_t *dims, int N, int R, cpm_dtype dt, char *base, si
         off += align_up(bytes);
         return p;
     };
-    const TreePlan t = plan_tree(dims, N, R);
+    TreePlan t = plan_tree(dims, N, R);
+    // the intermediates are reserved whenever a 16-byte aligned tensor
+    // would take the split (an unaligned one may then leave them unused)
+    t.use = t.use && tree_reach_ok(t, (const void *)(uintptr_t)4096, R, dt);
     size_t m = max_mttkrp_ws(dims, N, R, dt);
     if (t.use) {
         const size_t fz = dtype_f_bytes(dt);
@@ -973,7 +1017,7 @@ cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *co
             ++nwant;
             (n < tree.s ? want_left : want_right) = true;
         }
-    tree.use = tree.use && nwant >= 3 && tree_reach_ok(tree, X, R, dt);
+    tree.use = tree.use && nwant >= 3 && w.TL && tree_reach_ok(tree, X, R, dt);
     if (tree.use) {
         if (want_left) {
             s = tree_pass(tree, true, X, factors, R, dt, w, stream);
@@ -1469,7 +1513,7 @@ int cpm_mttkrp_describe(const int64_t *dims, int N, int R, int mode, cpm_dtype d
     char name[96];
     switch (p.kind) {
     case kLeft32: snprintf(name, sizeof(name), "k_left32<NC=%d,WM=%d>", p.NB, p.MB); break;
-    case kRight32: snprintf(name, sizeof(name), "k_right32<NC=%d,TJ=%d,WJ=1>", p.NB, p.Q); break;
+    case kRight32: snprintf(name, sizeof(name), "k_right32<NC=%d,TJ=%d,WJ=%d>", p.NB, p.Q, p.MB); break;
     case kLeft:
         snprintf(name, sizeof(name), "k_contract_left<%s,NB=%d,MB=%d,V4=%d,Q=%d>", dt == CPM_F64 ? "f64" : "f32",
                  p.NB, p.MB, (int)p.v4, p.Q);
@@ -1787,7 +1831,7 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
     // factors, which are not updated before mode s, and T_R is formed after
     // the left group's updates: the sweep stays Gauss-Seidel.
     TreePlan tree = plan_tree(dims, N, R);
-    tree.use = tree.use && tree_reach_ok(tree, X, R, dt);
+    tree.use = tree.use && w.all.TL && tree_reach_ok(tree, X, R, dt);
     const void *const *cf = (const void *const *)factors;
     for (int n = 0; n < N; ++n) {
         if (tree.use) {
@@ -1902,7 +1946,7 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
             (n < tree.s ? want_left : want_right) = true;
         }
     // the reuse pays once three or more modes are wanted
-    tree.use = tree.use && nwant >= 3 && tree_reach_ok(tree, X, R, dt);
+    tree.use = tree.use && nwant >= 3 && w.all.TL && tree_reach_ok(tree, X, R, dt);
     if (tree.use) {
         if (want_left) {
             s = tree_pass(tree, true, X, factors, R, dt, w.all, stream);

@@ -211,10 +211,19 @@ def test_mttkrp_all_workspace_holds_the_group_intermediates():
     per_mode = max(_abi.mttkrp_workspace_bytes(d5, 32, n, _abi.CPM_F32) for n in range(5))
     assert inter + per_mode <= ws5 <= inter + per_mode + (64 << 20)
     assert _abi.mttkrp_all_workspace_bytes(d5, 32, _abi.CPM_F64) >= 2 * inter
-    # 3-way: each mode is an ordinary MTTKRP
+    # 3-way 512^3 at R = 32: modes 0 and 1 share the pass over the
+    # (512 * 512, 512) view, whose 262144 x 32 intermediate is reserved;
+    # split bf16 (no such pass) keeps one ordinary MTTKRP per mode
     d3 = (512, 512, 512)
-    assert _abi.mttkrp_all_workspace_bytes(d3, 32, _abi.CPM_F32) == max(
-        _abi.mttkrp_workspace_bytes(d3, 32, n, _abi.CPM_F32) for n in range(3))
+    per3 = max(_abi.mttkrp_workspace_bytes(d3, 32, n, _abi.CPM_F32) for n in range(3))
+    assert _abi.mttkrp_all_workspace_bytes(d3, 32, _abi.CPM_F32) >= 512 * 512 * 32 * 4 + 512 * 32 * 4
+    assert _abi.mttkrp_all_workspace_bytes(d3, 32, _abi.CPM_BF16X2) == max(
+        _abi.mttkrp_workspace_bytes(d3, 32, n, _abi.CPM_BF16X2) for n in range(3))
+    # small 3-way tensors: no reuse
+    d3s = (40, 30, 20)
+    assert _abi.mttkrp_all_workspace_bytes(d3s, 16, _abi.CPM_F32) == max(
+        _abi.mttkrp_workspace_bytes(d3s, 16, n, _abi.CPM_F32) for n in range(3))
+    assert per3 > 0
     # intermediates as large as X itself: no reuse, ordinary MTTKRPs
     d = (2, 2, 2, 100000)
     assert _abi.mttkrp_all_workspace_bytes(d, 32, _abi.CPM_F32) == max(

@@ -215,3 +215,67 @@ def test_als_sweep_with_reuse_split_bf16():
     for n, (g, r) in enumerate(zip(Ud, ref)):
         assert rel_err(g.cpu().numpy(), r) <= 1e-4 * kap, n
     assert fit == pytest.approx(fit_ref, abs=1e-4)
+
+
+# 3-way tensors: modes 0 and 1 from one right-first pass over the
+# (I_0 I_1, I_2) view (each wave its own j range over the whole I_2, the
+# wide intermediate written directly), mode 2 from an ordinary pass
+THREE_WAY = [((512, 256, 200), (13, 32, 40)), ((1024, 130, 150), (20,)), ((520, 256, 300), (32,))]
+
+
+@pytest.mark.parametrize("dims,ranks", THREE_WAY)
+def test_mttkrp_all_three_way_reuse_matches_oracle(dims, ranks):
+    for R in ranks:
+        announce("mttkrp_all 3-way", dims, R)
+        assert uses_reuse(dims, R, _abi.CPM_F32), (dims, R)
+        X, U = make_case(dims, R, seed=sum(dims) + R)
+        outs = _abi.mttkrp_all(X.cuda(), dims, [u.cuda() for u in U])
+        torch.cuda.synchronize()
+        Xh, Uh = X.numpy().ravel(), [u.numpy() for u in U]
+        for n in range(3):
+            err = rel_err(outs[n].cpu().numpy(), O.mttkrp(Xh, dims, Uh, n))
+            assert err <= TOL["f32"], (dims, R, n, err)
+
+
+def test_als_sweep_three_way_reuse_matches_oracle():
+    """Gauss-Seidel with the 3-way split: modes 0 and 1 from the
+    intermediate formed before any update (it depends on U_2 only), mode 2
+    from an ordinary pass after them."""
+    dims, R = (512, 256, 200), 13
+    assert uses_reuse(dims, R, _abi.CPM_F32)
+    X = inputs.uniform_tensor(dims, seed=31, dtype=torch.float32)
+    U = inputs.normal_factors(dims, R, seed=32, dtype=torch.float32)
+    Uh = [u.numpy().astype(np.float64) for u in U]
+    ref, fit_ref = O.cp_als_step(X.numpy().ravel(), dims, Uh)
+    kap = 1.0
+    for n in range(3):
+        H = np.ones((R, R))
+        for m in range(3):
+            if m != n:
+                H *= ref[m].T @ ref[m]
+        kap = max(kap, np.linalg.cond(H))
+    Ud = [u.cuda() for u in U]
+    fit = _abi.cp_als_step(X.cuda(), dims, Ud)
+    for n, (g, r) in enumerate(zip(Ud, ref)):
+        assert rel_err(g.cpu().numpy(), r) <= 1e-5 * kap, (n, rel_err(g.cpu().numpy(), r))
+    assert fit == pytest.approx(fit_ref, abs=1e-5)
+
+
+def test_cp_grad_three_way_reuse_matches_oracle():
+    dims, R = (1024, 130, 150), 20
+    assert uses_reuse(dims, R, _abi.CPM_F32)
+    X, U = make_case(dims, R, seed=41)
+    Xh = X.numpy().ravel()
+    Uh = [u.numpy().astype(np.float64) for u in U]
+    xn = O.xnorm2(Xh, dims)
+    grads, loss = _abi.cp_grad(X.cuda(), dims, [u.cuda() for u in U], xnorm2=xn)
+    torch.cuda.synchronize()
+    G, ld, _ = O.cp_grad(Xh, dims, Uh)
+    for n in range(3):
+        H = np.ones((R, R))
+        for k in range(3):
+            if k != n:
+                H *= Uh[k].T @ Uh[k]
+        scale = np.linalg.norm(Uh[n] @ H) + np.linalg.norm(G[n] + Uh[n] @ H)
+        assert np.linalg.norm(grads[n].cpu().numpy() - G[n]) / scale <= TOL["f32"], n
+    assert abs(loss.item() - ld) <= 1e-5 * xn
