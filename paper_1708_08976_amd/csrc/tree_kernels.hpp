@@ -41,7 +41,8 @@ __device__ inline T krp_slow_value(const Krp<T> &k, int R, int64_t g, int c) {
 // Algorithm 1 walks Khatri-Rao rows: the product of the slower factors is
 // held and refreshed only when the fastest index wraps, and the T row
 // advances by one (by Ll * (It - 1) more when b wraps).  The block's sum is
-// formed in LDS in a fixed order (waves, then sub-rows), in float64.  With
+// formed in a fixed order in float64: a butterfly over each wave's
+// sub-rows, then the four waves in order through LDS.  With
 // grid.y == 1 the result goes to M directly, otherwise to slice blockIdx.y
 // of the partial buffer [grid.y][It][R], summed afterwards in slice order.
 constexpr int kLeafBatch = 8;
@@ -106,12 +107,14 @@ __global__ __launch_bounds__(kThreads) void k_tree_leaf(const T *__restrict__ Tm
                 for (int u = 0; u < kLeafBatch; ++u) acc += v[u] * (double)ws[u];
             }
         }
-        red[tid] = acc;
+        // the wave's sub-rows first (a butterfly over the lanes that hold the
+        // same columns: a fixed pattern, so the sum is reproducible), then
+        // the four waves in order
+        for (int off = RC; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
+        if (lane < RC) red[wave * 64 + lane] = acc;
         __syncthreads();
         if (tid < RC) {
-            double s = 0.0;
-            for (int w = 0; w < 4; ++w)
-                for (int q = 0; q < subs; ++q) s += red[w * 64 + q * RC + tid];
+            const double s = ((red[tid] + red[64 + tid]) + red[128 + tid]) + red[192 + tid];
             const int oc = (int)blockIdx.z * RC + tid;
             if (oc < R) out[((int64_t)blockIdx.y * It + i) * R + oc] = (T)s;
         }
@@ -193,15 +196,20 @@ __global__ __launch_bounds__(kThreads) void k_tree_leaf4(const float *__restrict
                     for (int e = 0; e < 4; ++e) acc[e] += (double)v[u][e] * (double)ws[u][e];
             }
         }
+        // the wave's sub-rows first (a butterfly over the lanes that hold the
+        // same columns: a fixed pattern, so the sum is reproducible), then
+        // the four waves in order
+        for (int off = RC; off < 64; off <<= 1)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) red[e][tid] = acc[e];
+            for (int e = 0; e < 4; ++e) acc[e] += __shfl_xor(acc[e], off);
+        if (lane < RC)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[e][wave * 64 + lane] = acc[e];
         __syncthreads();
         if (tid < RC) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                double s = 0.0;
-                for (int w = 0; w < 4; ++w)
-                    for (int q = 0; q < subs; ++q) s += red[e][w * 64 + q * RC + tid];
+                const double s = ((red[e][tid] + red[e][64 + tid]) + red[e][128 + tid]) + red[e][192 + tid];
                 const int oc = c4 + e;
                 if (oc < R) out[((int64_t)blockIdx.y * It + i) * R + oc] = (float)s;
             }
