@@ -143,8 +143,9 @@ cpm_status mttkrp_scratch(const void *X, const int64_t *dims, int N, const void 
  * type -- the contraction kernel with its template parameters, its grid,
  * LDS bytes, Khatri-Rao chunk, inner/outer split (Section 4.1's reuse at
  * tile level), split-K count and whether the fixed-order reduction runs.
- * X is used only for its address alignment (never dereferenced; null means
- * 16-byte aligned is not assumed).  Host only, launches nothing.  Returns
+ * X is used only for its address alignment (never dereferenced; null
+ * counts as aligned, like any multiple of 16).  Host only, launches
+ * nothing.  Returns
  * a cpm_status (CPM_EINVAL for bad arguments or an empty buffer).
  */
 int cpm_mttkrp_describe(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const void *X, char *buf,
@@ -161,14 +162,18 @@ size_t cpm_mttkrp_all_workspace_bytes(const int64_t *dims, int N, int R, cpm_dty
  * across modes that the Conclusion names as the next step (after Phan et
  * al.).  X, dims, factors, R, dt as for `mttkrp`, except that every factor
  * is read.  outs: host array of N device pointers, outs[n] an I_n x R
- * output or null to skip mode n.  From N = 4 on, when three or more modes
- * are requested, the modes are split into a left group [0, s) and a right
- * group [s, N): one pass over X contracts the right group and one the left,
- * each leaving an intermediate of (entries of its group) x R values in the
- * workspace, and every requested mode then follows from its group's
- * intermediate -- two passes over X instead of one per mode.  The split is
- * chosen so that the intermediates move fewer entries than one pass over X;
- * otherwise (and for N < 4) each mode is an ordinary `mttkrp`.  The result
+ * output or null to skip mode n.  When three or more modes are requested,
+ * the modes are split into a left group [0, s) and a right group [s, N):
+ * one pass over X contracts the right group and one the left, each leaving
+ * an intermediate of (entries of its group) x R values in the workspace,
+ * and every requested mode then follows from its group's intermediate --
+ * two passes over X instead of one per mode.  From N = 4 on the split is
+ * chosen so that the intermediates move fewer entries than one pass over X.
+ * For N = 3 the split is {0, 1} | {2}, used under the same rule and only
+ * where the pass over the (I_0 I_1, I_2) view runs as fast as a single-mode
+ * call (float32, I_0 I_1 of about 131072 or more, I_2 up to 512; the query
+ * `cpm_mttkrp_all_workspace_bytes` reserves room for it exactly then).
+ * Otherwise (and for N = 2) each mode is an ordinary `mttkrp`.  The result
  * agrees with `mttkrp` to rounding (a different summation order) and is
  * bitwise reproducible run to run.  Stream-ordered, no synchronisation.
  */
@@ -275,7 +280,8 @@ size_t cpm_cp_grad_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype 
  * fit_out: host pointer, may be null; receives 1 - ||X - Y|| / ||X|| of the
  * updated model (from ||X||^2 - 2 <M_{N-1}, U_{N-1}> + sum(Hadamard of all
  * Grams), accumulated in float64).  Waits for the stream once.
- * From N = 4 on the MTTKRPs come from the two passes of `mttkrp_all`: the
+ * Where `mttkrp_all` would split the modes, the MTTKRPs come from its two
+ * passes: the
  * left group's intermediate depends only on factors not yet updated when
  * it is formed, and the right group's is formed after the left group's
  * updates, so the sweep is the same Gauss-Seidel order.
@@ -293,8 +299,8 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
  * 1/2 (||X||^2 - 2 <MTTKRP_{N-1}, U_{N-1}> + sum(Hadamard of all Grams)),
  * accumulated in float64, the residual itself never being formed.
  * xnorm2: ||X||_F^2 if known, negative to compute it on the device.
- * The MTTKRPs are formed as by `mttkrp_all` (two passes over X from N = 4
- * on when three or more modes are wanted).
+ * The MTTKRPs are formed as by `mttkrp_all` (two passes over X where it
+ * splits the modes).
  * R <= 256: the gradient needs no factorisation.
  */
 cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const *factors, int R,

@@ -789,9 +789,10 @@ size_t max_mttkrp_ws(const int64_t *dims, int N, int R, cpm_dtype dt) {
 // X viewed as (L, I_s, ..., I_{N-1}) with L = I_0 ... I_{s-1}, mode 0, gives
 // T_L (L x R).  Pass B contracts the left group: X viewed as (I_0, ...,
 // I_{s-1}, Rr), mode s, gives T_R (Rr x R).  Each mode's MTTKRP is then a
-// leaf of its group's intermediate (k_tree_leaf).  Used from N = 4 on, and
-// only while the intermediates (written once, read by every leaf of their
-// group) move fewer entries than one pass over X.
+// leaf of its group's intermediate (k_tree_leaf).  Used only while the
+// intermediates (written once, read by every leaf of their group) move fewer
+// entries than one pass over X; for N = 3 the split is fixed at s = 2 and
+// further needs pass A to plan as the wide right-first kernel (tree_reach_ok).
 struct TreePlan {
     bool use = false;
     int s = 0, nA = 0, nB = 0;
@@ -894,6 +895,29 @@ LeafShape leaf_shape(const int64_t *g, int m, int t, int R, bool vec) {
     return q;
 }
 
+// Both leaves of a two-mode group in one pass (k_pair_leaf): the group's
+// first mode has B values, its second A.  Float32 intermediates (float32 and
+// split-bf16 paths) with R a multiple of 4 up to 128.
+struct PairShape {
+    bool ok = false;
+    int wpw = 0;
+    int64_t gx = 0, gy = 0;   // b tiles (slices of M_a), a tiles (slices of M_b)
+    size_t bytes_a = 0, bytes_b = 0;  // partial slices (0 when one slice is the result)
+};
+
+PairShape pair_shape(int64_t B, int64_t A, int R, cpm_dtype dt) {
+    PairShape q;
+    if (dt == CPM_F64 || R % 4 != 0 || R > 128) return q;
+    q.wpw = R <= 32 ? 8 : R <= 64 ? 4 : 2;
+    q.gx = ceil_div(B, kPairTB);
+    q.gy = ceil_div(A, 4 * kPairTA);
+    if (q.gy > 65535 || (A * B + kPairTB) * R * 4 > (int64_t)kRsrcRange) return q;
+    q.bytes_a = q.gx > 1 ? align_up((size_t)q.gx * A * R * sizeof(float)) : 0;
+    q.bytes_b = q.gy > 1 ? align_up((size_t)q.gy * B * R * sizeof(float)) : 0;
+    q.ok = true;
+    return q;
+}
+
 size_t leaf_partial_bytes(const int64_t *dims, int N, int R, cpm_dtype dt, const TreePlan &t) {
     size_t b = 0;
     for (int n = 0; n < N; ++n) {
@@ -902,6 +926,10 @@ size_t leaf_partial_bytes(const int64_t *dims, int N, int R, cpm_dtype dt, const
             if (vec && (R % 4 != 0 || dt == CPM_F64)) continue;
             const LeafShape q = leaf_shape(dims + g0, g1 - g0, n - g0, R, vec);
             if (q.S > 1) b = std::max(b, (size_t)q.S * q.It * R * dtype_f_bytes(dt));
+        }
+        if (g1 - g0 == 2) {
+            const PairShape pq = pair_shape(dims[g0], dims[g0 + 1], R, dt);
+            if (pq.ok) b = std::max(b, pq.bytes_a + pq.bytes_b);
         }
     }
     return b;
@@ -942,20 +970,22 @@ AllWs layout_all(const int64_t *dims, int N, int R, cpm_dtype dt, char *base, si
 }
 
 // Pass A (left = true: T_L from the right group's factors) or pass B.
+// dst, when non-null, receives the intermediate instead of the workspace
+// (a one-mode group's intermediate is that mode's MTTKRP).
 cpm_status tree_pass(const TreePlan &t, bool left, const void *X, const void *const *factors, int R, cpm_dtype dt,
-                     const AllWs &w, hipStream_t st) {
+                     const AllWs &w, hipStream_t st, void *dst = nullptr) {
     const void *f[CPM_MAX_MODES];
     if (left) {
         const int N = t.nA + t.s - 1;
         f[0] = nullptr;
         for (int k = t.s; k < N; ++k) f[k - t.s + 1] = factors[k];
         const Plan p = make_plan(t.dA, t.nA, R, 0, dt, X);
-        return run_mttkrp(p, X, t.dA, t.nA, f, R, 0, w.TL, dt, w.mws, st);
+        return run_mttkrp(p, X, t.dA, t.nA, f, R, 0, dst ? dst : w.TL, dt, w.mws, st);
     }
     for (int k = 0; k < t.s; ++k) f[k] = factors[k];
     f[t.s] = nullptr;
     const Plan p = make_plan(t.dB, t.nB, R, t.s, dt, X);
-    return run_mttkrp(p, X, t.dB, t.nB, f, R, t.s, w.TR, dt, w.mws, st);
+    return run_mttkrp(p, X, t.dB, t.nB, f, R, t.s, dst ? dst : w.TR, dt, w.mws, st);
 }
 
 template <typename T>
@@ -1004,6 +1034,46 @@ cpm_status tree_leaf(const TreePlan &t, const int64_t *dims, int N, const void *
     return tree_leaf_t<float>(t, dims, N, factors, R, n, w, (float *)out, st);
 }
 
+// Whether mode n is alone in its group (its intermediate is its MTTKRP).
+bool tree_single(const TreePlan &t, int N, int n) { return n < t.s ? t.s == 1 : t.s == N - 1; }
+
+// Both MTTKRPs of a two-mode group [g0, g0 + 2) from one pass over its
+// intermediate, into out_fast (mode g0) and out_slow (mode g0 + 1).  Sets
+// *done = false, launching nothing, when the shape or an alignment does not
+// allow it (the caller then runs the two single-mode leaves).
+cpm_status tree_pair_leaf(const TreePlan &t, const int64_t *dims, const void *const *factors, int R, int g0,
+                          cpm_dtype dt, const AllWs &w, void *out_fast, void *out_slow, hipStream_t st,
+                          bool *done) {
+    *done = false;
+    const int64_t B = dims[g0], A = dims[g0 + 1];
+    const PairShape q = pair_shape(B, A, R, dt);
+    const float *Tm = (const float *)(g0 == 0 ? w.TL : w.TR);
+    if (!q.ok || !Tm) return CPM_OK;
+    float *PA = q.bytes_a ? (float *)w.leaf : (float *)out_slow;
+    float *PB = q.bytes_b ? (float *)((char *)w.leaf + q.bytes_a) : (float *)out_fast;
+    for (const void *p : {(const void *)Tm, factors[g0], factors[g0 + 1], (const void *)PA})
+        if ((uintptr_t)p % 16 != 0) return CPM_OK;
+    const dim3 grid((unsigned)q.gx, (unsigned)q.gy);
+    const float *Ub = (const float *)factors[g0], *Ua = (const float *)factors[g0 + 1];
+    if (q.wpw == 8)
+        hipLaunchKernelGGL(k_pair_leaf<8>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, PA, PB);
+    else if (q.wpw == 4)
+        hipLaunchKernelGGL(k_pair_leaf<4>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, PA, PB);
+    else
+        hipLaunchKernelGGL(k_pair_leaf<2>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, PA, PB);
+    LAUNCH_CHECK("k_pair_leaf");
+    const int64_t blocks_a = q.bytes_a ? ceil_div(A * R, 64) : 0;
+    const int64_t blocks_b = q.bytes_b ? ceil_div(B * R, 64) : 0;
+    if (blocks_a + blocks_b > 0) {
+        hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)(blocks_a + blocks_b)), dim3(kThreads), 0, st, PA,
+                           q.bytes_a ? q.gx : (int64_t)0, A, (float *)out_slow, PB, q.bytes_b ? q.gy : (int64_t)0,
+                           B, (float *)out_fast, R, blocks_a);
+        LAUNCH_CHECK("k_pair_reduce");
+    }
+    *done = true;
+    return CPM_OK;
+}
+
 // Every requested mode's MTTKRP (arguments validated, workspace laid out):
 // the two-group reuse when it pays, otherwise one ordinary MTTKRP per mode.
 cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
@@ -1018,18 +1088,35 @@ cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *co
             (n < tree.s ? want_left : want_right) = true;
         }
     tree.use = tree.use && nwant >= 3 && w.TL && tree_reach_ok(tree, X, R, dt);
+    bool done[CPM_MAX_MODES] = {};
     if (tree.use) {
+        // a one-mode group's intermediate is that mode's MTTKRP: its pass
+        // writes the output directly
         if (want_left) {
-            s = tree_pass(tree, true, X, factors, R, dt, w, stream);
+            const bool one = tree_single(tree, N, 0);
+            s = tree_pass(tree, true, X, factors, R, dt, w, stream, one ? outs[0] : nullptr);
             if (s) return s;
+            done[0] = one;
         }
         if (want_right) {
-            s = tree_pass(tree, false, X, factors, R, dt, w, stream);
+            const bool one = tree_single(tree, N, N - 1);
+            s = tree_pass(tree, false, X, factors, R, dt, w, stream, one ? outs[N - 1] : nullptr);
             if (s) return s;
+            done[N - 1] = one;
+        }
+        // a two-mode group with both modes wanted: one pass over its
+        // intermediate for both
+        for (int g0 : {0, tree.s}) {
+            const int g1 = g0 == 0 ? tree.s : N;
+            if (g1 - g0 != 2 || !outs[g0] || !outs[g0 + 1] || dt == CPM_F64) continue;
+            bool pair = false;
+            s = tree_pair_leaf(tree, dims, factors, R, g0, dt, w, outs[g0], outs[g0 + 1], stream, &pair);
+            if (s) return s;
+            done[g0] = done[g0 + 1] = pair;
         }
     }
     for (int n = 0; n < N; ++n) {
-        if (!outs[n]) continue;
+        if (!outs[n] || done[n]) continue;
         if (tree.use) {
             s = tree_leaf(tree, dims, N, factors, R, n, dt, w, outs[n], stream);
         } else {
@@ -1318,7 +1405,7 @@ struct SolveWs {
     int *status;
     double *xnorm2, *inner, *result;
     double *grams, *gpart, *H, *L, *Lt, *hpart;
-    void *M, *snap, *sumsq;
+    void *M, *M2, *snap, *sumsq;  // M2: the second output of a two-mode leaf (gradient only)
     AllWs all;  // intermediates of the all-mode MTTKRP and the MTTKRP workspace
     size_t need;
 };
@@ -1367,6 +1454,7 @@ SolveWs layout_solve(const int64_t *dims, int N, int R, cpm_dtype dt, char *base
     w.Lt = (double *)take((size_t)R * R * sizeof(double));
     w.hpart = (double *)take((size_t)kHadsumBlocks * sizeof(double));
     w.M = take((size_t)maxI * R * fz);
+    w.M2 = snapshot ? nullptr : take((size_t)maxI * R * fz);
     w.snap = snapshot ? take((size_t)sumI * R * fz) : nullptr;
     w.sumsq = take((size_t)kSumsqBlocks * sizeof(double));
     w.all = layout_all(dims, N, R, dt, base, off);
@@ -1835,11 +1923,12 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
     const void *const *cf = (const void *const *)factors;
     for (int n = 0; n < N; ++n) {
         if (tree.use) {
+            const bool one = tree_single(tree, N, n);
             if (n == 0 || n == tree.s) {
-                s = tree_pass(tree, n == 0, X, cf, R, dt, w.all, stream);
+                s = tree_pass(tree, n == 0, X, cf, R, dt, w.all, stream, one ? w.M : nullptr);
                 if (s) return s;
             }
-            s = tree_leaf(tree, dims, N, cf, R, n, dt, w.all, w.M, stream);
+            if (!one) s = tree_leaf(tree, dims, N, cf, R, n, dt, w.all, w.M, stream);
         } else {
             Plan p = make_plan(dims, N, R, n, dt, X);
             s = run_mttkrp(p, X, dims, N, cf, R, n, w.M, dt, w.all.mws, stream);
@@ -1957,19 +2046,36 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
             if (s) return s;
         }
     }
+    int in_m2 = -1;  // the mode whose MTTKRP a two-mode leaf left in M2
     for (int n = 0; n < N; ++n) {
         const bool want_grad = grads && grads[n];
         const bool want_inner = loss_dev && n == N - 1;
         if (!want_grad && !want_inner) continue;
+        void *M = w.M;
         if (tree.use) {
-            s = tree_leaf(tree, dims, N, factors, R, n, dt, w.all, w.M, stream);
+            // a one-mode group's intermediate is its MTTKRP; a two-mode
+            // group forms both of its MTTKRPs in one pass (the second in M2)
+            const int g0 = n < tree.s ? 0 : tree.s, g1 = n < tree.s ? tree.s : N;
+            if (g1 - g0 == 1) {
+                M = n < tree.s ? w.all.TL : w.all.TR;
+            } else if (n == in_m2) {
+                M = w.M2;
+            } else {
+                bool pair = false;
+                if (n == g0 && g1 - g0 == 2 && wanted(n + 1) && dt != CPM_F64) {
+                    s = tree_pair_leaf(tree, dims, factors, R, g0, dt, w.all, w.M, w.M2, stream, &pair);
+                    if (s) return s;
+                    if (pair) in_m2 = n + 1;
+                }
+                if (!pair) s = tree_leaf(tree, dims, N, factors, R, n, dt, w.all, w.M, stream);
+            }
         } else {
             Plan p = make_plan(dims, N, R, n, dt, X);
             s = run_mttkrp(p, X, dims, N, factors, R, n, w.M, dt, w.all.mws, stream);
         }
         if (s) return s;
         if (want_inner) {
-            s = dot_enqueue(w.M, factors[n], dims[n] * R, dt, (double *)w.sumsq, w.inner, stream);
+            s = dot_enqueue(M, factors[n], dims[n] * R, dt, (double *)w.sumsq, w.inner, stream);
             if (s) return s;
         }
         if (want_grad) {
@@ -1978,11 +2084,11 @@ cpm_status cp_grad(const void *X, const int64_t *dims, int N, const void *const 
             const unsigned blocks = (unsigned)ceil_div(dims[n] * R, 64);
             if (dt == CPM_F64)
                 hipLaunchKernelGGL(k_grad<double>, dim3(blocks), dim3(kThreads), 0, stream,
-                                   (const double *)factors[n], w.H, (const double *)w.M, dims[n], R,
+                                   (const double *)factors[n], w.H, (const double *)M, dims[n], R,
                                    (double *)grads[n]);
             else
                 hipLaunchKernelGGL(k_grad<float>, dim3(blocks), dim3(kThreads), 0, stream, (const float *)factors[n],
-                                   w.H, (const float *)w.M, dims[n], R, (float *)grads[n]);
+                                   w.H, (const float *)M, dims[n], R, (float *)grads[n]);
             LAUNCH_CHECK("k_grad");
         }
     }

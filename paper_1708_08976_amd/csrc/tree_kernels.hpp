@@ -218,4 +218,157 @@ __global__ __launch_bounds__(kThreads) void k_tree_leaf4(const float *__restrict
     }
 }
 
+// Both MTTKRPs of a two-mode group from one pass over its intermediate.
+// The rows of T are l = b + B * a (b the group's first mode, a its second):
+//   M_b(b, c) = sum_a T(l, c) U_a(a, c),   M_a(a, c) = sum_b T(l, c) U_b(b, c).
+// A wave covers 4 * RC rank columns with RC = 64 / WPW lanes of 4 columns
+// each, so WPW workers share it.  A work-group takes kPairTB values of b
+// and 4 * kPairTA values of a (kPairTA per wave); worker w of a wave takes
+// b = b0 + w + WPW * j for j < kPairTB / WPW, so one load instruction reads
+// WPW consecutive rows of T.  The loads of WPW values of a are issued
+// together, then:
+//   M_a: each worker adds its b products in j order; the wave's workers
+//     then reduce-scatter the WPW rows (a butterfly that halves the rows
+//     each lane keeps at every step: worker w ends with the sum of row w),
+//     written to slice blockIdx.x of PA [gridDim.x][A][R];
+//   M_b: each worker adds over its wave's a values in order; the four
+//     waves are added in order through LDS and written to slice blockIdx.y
+//     of PB [gridDim.y][B][R].
+// All sums in float64 in a fixed order; k_pair_reduce adds the slices.  A
+// grid dimension of 1 makes the slice the result itself.  Needs R a
+// multiple of 4, R <= 4 * RC, 16-byte aligned T, factors and PA, and
+// (A * B + kPairTB) * R * 4 below 2^32 (buffer offsets).
+constexpr int kPairTA = 8;
+constexpr int kPairTB = 16;
+template <int WPW>
+__global__ __launch_bounds__(kThreads) void k_pair_leaf(const float *__restrict__ Tm, int64_t A, int64_t B,
+                                                        const float *__restrict__ Ua,
+                                                        const float *__restrict__ Ub, int R,
+                                                        float *__restrict__ PA, float *__restrict__ PB) {
+    constexpr int RC = 64 / WPW;
+    constexpr int KB = kPairTB / WPW;
+    __shared__ double red[4][kPairTB][4 * RC];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int w = lane / RC;
+    const int c4 = 4 * (lane % RC);
+    const bool col_ok = c4 < R;
+    const int cc = col_ok ? c4 : 0;
+    const int64_t b0 = (int64_t)blockIdx.x * kPairTB;
+    const int64_t a0 = (int64_t)blockIdx.y * (4 * kPairTA) + wave * kPairTA;
+    const f32x4 zeros = {0.f, 0.f, 0.f, 0.f};
+    // T and U_a through buffer resources: a lane offset plus a wave-uniform
+    // row offset.  The host keeps every offset of T below 2^32; lanes past B
+    // or R read a neighbouring row (or zeros past the end) and are masked.
+    const rsrc_t rt = make_rsrc(Tm, (uint32_t)(A * B * R * 4));
+    const rsrc_t ru = make_rsrc(Ua, (uint32_t)(A * R * 4));
+    const uint32_t lane_off = (uint32_t)((w * R + c4) * 4);
+    f32x4 ub[KB];
+    bool bok[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        const int64_t b = b0 + w + WPW * j;
+        bok[j] = col_ok && b < B;
+        ub[j] = bok[j] ? *reinterpret_cast<const f32x4 *>(Ub + b * R + cc) : zeros;
+    }
+    double accb[KB][4];
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) accb[j][e] = 0.0;
+    // one chunk of loads in flight per wave: the resident waves overlap them
+#pragma unroll 1
+    for (int ac = 0; ac < kPairTA; ac += WPW) {
+        f32x4 v[WPW][KB];
+#pragma unroll
+        for (int u = 0; u < WPW; ++u) {
+            const int64_t a = a0 + ac + u;
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                const uint32_t row_off = (uint32_t)(((a * B) + b0 + WPW * j) * R * 4);
+                const f32x4 x = __builtin_bit_cast(
+                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(rt, lane_off, (int)row_off, kStream));
+                v[u][j] = (a < A && bok[j]) ? x : zeros;
+            }
+        }
+        double pa[WPW][4];
+#pragma unroll
+        for (int u = 0; u < WPW; ++u) {
+            const int64_t a = a0 + ac + u;
+            const f32x4 x = __builtin_bit_cast(
+                f32x4, __builtin_amdgcn_raw_buffer_load_b128(ru, (uint32_t)(c4 * 4), (int)(uint32_t)(a * R * 4), 0));
+            const f32x4 ua = (a < A && col_ok) ? x : zeros;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    s += (double)v[u][j][e] * (double)ub[j][e];
+                    accb[j][e] += (double)v[u][j][e] * (double)ua[e];
+                }
+                pa[u][e] = s;
+            }
+        }
+        // reduce-scatter over the wave's workers: at the step of bit m a
+        // lane keeps the half of its rows selected by bit m of w and adds
+        // the partner's copy of that half
+#pragma unroll
+        for (int m = WPW / 2; m >= 1; m >>= 1) {
+            const bool hi = (w & m) != 0;
+#pragma unroll
+            for (int i = 0; i < m; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double keep = hi ? pa[i + m][e] : pa[i][e];
+                    const double send = hi ? pa[i][e] : pa[i + m][e];
+                    pa[i][e] = keep + __shfl_xor(send, m * RC);
+                }
+        }
+        const int64_t a = a0 + ac + w;
+        if (a < A && col_ok) {
+            const f32x4 o = {(float)pa[0][0], (float)pa[0][1], (float)pa[0][2], (float)pa[0][3]};
+            *reinterpret_cast<f32x4 *>(PA + ((int64_t)blockIdx.x * A + a) * R + c4) = o;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[wave][w + WPW * j][c4 + e] = accb[j][e];
+    __syncthreads();
+    for (int q = tid; q < kPairTB * R; q += kThreads) {
+        const int bl = q / R, c = q % R;
+        const int64_t b = b0 + bl;
+        if (b < B)
+            PB[((int64_t)blockIdx.y * B + b) * R + c] =
+                (float)(((red[0][bl][c] + red[1][bl][c]) + red[2][bl][c]) + red[3][bl][c]);
+    }
+}
+
+// The slice sums of k_pair_leaf for both outputs in one launch: blocks
+// [0, blocks_a) take 64 consecutive entries of M_a, the rest of M_b.  The
+// four waves of a block take interleaved slices and are added in wave
+// order, in float64.  S == 0 skips that output (its slice was the result).
+__global__ __launch_bounds__(kThreads) void k_pair_reduce(const float *__restrict__ PA, int64_t SA, int64_t A,
+                                                          float *__restrict__ MA, const float *__restrict__ PB,
+                                                          int64_t SB, int64_t B, float *__restrict__ MB, int R,
+                                                          int64_t blocks_a) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool is_a = (int64_t)blockIdx.x < blocks_a;
+    const float *P = is_a ? PA : PB;
+    const int64_t S = is_a ? SA : SB;
+    const int64_t total = (is_a ? A : B) * R;
+    float *M = is_a ? MA : MB;
+    const int64_t e = ((int64_t)blockIdx.x - (is_a ? 0 : blocks_a)) * 64 + lane;
+    double s = 0.0;
+    if (e < total) {
+#pragma unroll 4
+        for (int64_t q = wave; q < S; q += 4) s += (double)P[q * total + e];
+    }
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && e < total) M[e] = (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+}
+
 }  // namespace cpm

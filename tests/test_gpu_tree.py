@@ -103,6 +103,43 @@ def test_mttkrp_all_bitwise_reproducible():
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
+def test_mttkrp_all_two_mode_groups_one_pass(dtype):
+    """Both MTTKRPs of a two-mode group from one pass over its intermediate
+    (float32 intermediates, R a multiple of 4 up to 128): every lane width
+    (R <= 32, <= 64, <= 128), rank columns past R in a lane block, ragged
+    b and a tiles, several slices per output.  A factor off 16-byte
+    alignment takes the one-mode leaves instead; both agree with the
+    oracle."""
+    dims = (37, 45, 21, 34)
+    code = CODES[dtype]
+    for R in (4, 12, 32, 36, 68, 100, 128):
+        announce("pair leaf", dtype, dims, R)
+        assert uses_reuse(dims, R, code), R
+        X, U, Xd, planes = case_tensors(dims, R, seed=R + 17, dtype=dtype)
+        if planes is None:
+            Xh, xt = X.numpy().ravel(), None
+        else:
+            Xh, xt = planes.numpy().view(np.uint16), O.BF16PAIR
+        Uh = [u.numpy() for u in U]
+        refs = [O.mttkrp(Xh, dims, Uh, n, xtype=xt) for n in range(4)]
+        Ud = [u.cuda() for u in U]
+        outs = _abi.mttkrp_all(Xd, dims, Ud, dtype=code)
+        again = _abi.mttkrp_all(Xd, dims, Ud, dtype=code)
+        # U_1 moved 4 bytes off 16-byte alignment
+        buf = torch.empty(dims[1] * R + 1, device="cuda")
+        u1 = buf[1:].view(dims[1], R)
+        u1.copy_(Ud[1])
+        assert u1.data_ptr() % 16 != 0
+        mis = _abi.mttkrp_all(Xd, dims, [Ud[0], u1, Ud[2], Ud[3]], dtype=code)
+        torch.cuda.synchronize()
+        for n in range(4):
+            assert torch.equal(outs[n], again[n]), (R, n)
+            for got in (outs[n], mis[n]):
+                err = rel_err(got.cpu().numpy(), refs[n])
+                assert err <= TOL[dtype], (R, n, err)
+
+
 @pytest.mark.parametrize("dims", [(40, 30, 20), (12, 12, 12, 12, 12)])
 def test_mttkrp_all_without_reuse_is_mttkrp(dims):
     """A 3-way tensor, or a rank too large for the reuse to pay: every mode
