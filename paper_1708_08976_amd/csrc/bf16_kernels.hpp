@@ -19,9 +19,11 @@ namespace cpm {
 
 __device__ inline bf16x8 as_bf16x8(f32x4 raw) { return __builtin_bit_cast(bf16x8, raw); }
 
-// One 16-byte buffer load of 8 consecutive bf16 values.
+// One 16-byte buffer load of 8 consecutive bf16 values.  The planes are
+// read without the non-temporal hint: with it, the left-first kernels on the
+// 256 x 256 x 512 x 32 tensor at R = 128 took 7-11% longer.
 __device__ inline f32x4 buf_load_raw16(rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kStream));
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
 // 8 consecutive bf16 values read one at a time (unaligned rows); lanes past
@@ -31,7 +33,7 @@ __device__ inline f32x4 buf_load_raw16_scalar(rsrc_t r, uint32_t off, int64_t l,
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const uint32_t oe = (off != kNoLoad && l + e < lend) ? off + 2 * e : kNoLoad;
-        v[e] = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, oe, 0, kStream);
+        v[e] = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, oe, 0, 0);
     }
     return __builtin_bit_cast(f32x4, v);
 }

@@ -895,12 +895,14 @@ LeafShape leaf_shape(const int64_t *g, int m, int t, int R, bool vec) {
     return q;
 }
 
+constexpr int64_t kPairGroups = 512;
+
 // Both leaves of a two-mode group in one pass (k_pair_leaf): the group's
 // first mode has B values, its second A.  Float32 intermediates (float32 and
 // split-bf16 paths) with R a multiple of 4 up to 128.
 struct PairShape {
     bool ok = false;
-    int wpw = 0;
+    int wpw = 0, ta = 0;      // workers per wave, a values per wave
     int64_t gx = 0, gy = 0;   // b tiles (slices of M_a), a tiles (slices of M_b)
     size_t bytes_a = 0, bytes_b = 0;  // partial slices (0 when one slice is the result)
 };
@@ -910,7 +912,11 @@ PairShape pair_shape(int64_t B, int64_t A, int R, cpm_dtype dt) {
     if (dt == CPM_F64 || R % 4 != 0 || R > 128) return q;
     q.wpw = R <= 32 ? 8 : R <= 64 ? 4 : 2;
     q.gx = ceil_div(B, kPairTB);
-    q.gy = ceil_div(A, 4 * kPairTA);
+    // fewer a values per wave (down to one chunk of wpw) while the grid
+    // would hold fewer than kPairGroups work-groups
+    q.ta = kPairTA;
+    while (q.ta > q.wpw && q.gx * ceil_div(A, 4 * q.ta) < kPairGroups) q.ta /= 2;
+    q.gy = ceil_div(A, 4 * q.ta);
     if (q.gy > 65535 || (A * B + kPairTB) * R * 4 > (int64_t)kRsrcRange) return q;
     q.bytes_a = q.gx > 1 ? align_up((size_t)q.gx * A * R * sizeof(float)) : 0;
     q.bytes_b = q.gy > 1 ? align_up((size_t)q.gy * B * R * sizeof(float)) : 0;
@@ -1056,11 +1062,11 @@ cpm_status tree_pair_leaf(const TreePlan &t, const int64_t *dims, const void *co
     const dim3 grid((unsigned)q.gx, (unsigned)q.gy);
     const float *Ub = (const float *)factors[g0], *Ua = (const float *)factors[g0 + 1];
     if (q.wpw == 8)
-        hipLaunchKernelGGL(k_pair_leaf<8>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, PA, PB);
+        hipLaunchKernelGGL(k_pair_leaf<8>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, q.ta, PA, PB);
     else if (q.wpw == 4)
-        hipLaunchKernelGGL(k_pair_leaf<4>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, PA, PB);
+        hipLaunchKernelGGL(k_pair_leaf<4>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, q.ta, PA, PB);
     else
-        hipLaunchKernelGGL(k_pair_leaf<2>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, PA, PB);
+        hipLaunchKernelGGL(k_pair_leaf<2>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, q.ta, PA, PB);
     LAUNCH_CHECK("k_pair_leaf");
     const int64_t blocks_a = q.bytes_a ? ceil_div(A * R, 64) : 0;
     const int64_t blocks_b = q.bytes_b ? ceil_div(B * R, 64) : 0;

@@ -126,10 +126,10 @@ constexpr uint32_t kNoLoad = 0xFFFFFFF0u;
 constexpr int kRsrcWord3 = 0x00020000;
 
 // Cache policy of the tensor's loads: bit 1 of a buffer load's policy
-// operand is the non-temporal hint.  The tensor is read once per pass, so
-// its loads carry it and leave the caches to factor rows and tiles.  On
-// MI355X a plain 512 MiB read ran at about 6.0 TB/s without the hint and
-// 6.9 TB/s with it.
+// operand is the non-temporal hint.  A float32 tensor is read once per
+// pass, so its loads carry it and leave the caches to factor rows and
+// tiles.  On MI355X a plain 512 MiB read ran at about 6.0 TB/s without the
+// hint and 6.9 TB/s with it (the split-bf16 planes are read without it).
 constexpr int kStream = 2;
 
 __device__ inline rsrc_t make_rsrc(const void *base, uint32_t bytes) {

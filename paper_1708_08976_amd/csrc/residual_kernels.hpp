@@ -91,8 +91,8 @@ __global__ __launch_bounds__(kThreads) void k_residual32(const void *__restrict_
         for (int j = 0; j < 16; ++j) {
             const uint32_t off = gl < glen ? ((uint32_t)acc32_row(lane, j) * (uint32_t)L + col) * ES : kNoLoad;
             if (BF) {
-                const uint16_t hb = __builtin_amdgcn_raw_buffer_load_b16(rx, off, 0, kStream);
-                const uint16_t lb = __builtin_amdgcn_raw_buffer_load_b16(rlo, off, 0, kStream);
+                const uint16_t hb = __builtin_amdgcn_raw_buffer_load_b16(rx, off, 0, 0);
+                const uint16_t lb = __builtin_amdgcn_raw_buffer_load_b16(rlo, off, 0, 0);
                 x[j] = bf16_bits_to_float(hb) + bf16_bits_to_float(lb);
             } else {
                 x[j] = buf_load1<kStream>(rx, off, 0.f);

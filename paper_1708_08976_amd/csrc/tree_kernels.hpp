@@ -223,10 +223,12 @@ __global__ __launch_bounds__(kThreads) void k_tree_leaf4(const float *__restrict
 //   M_b(b, c) = sum_a T(l, c) U_a(a, c),   M_a(a, c) = sum_b T(l, c) U_b(b, c).
 // A wave covers 4 * RC rank columns with RC = 64 / WPW lanes of 4 columns
 // each, so WPW workers share it.  A work-group takes kPairTB values of b
-// and 4 * kPairTA values of a (kPairTA per wave); worker w of a wave takes
+// and 4 * ta values of a (ta per wave); worker w of a wave takes
 // b = b0 + w + WPW * j for j < kPairTB / WPW, so one load instruction reads
-// WPW consecutive rows of T.  The loads of WPW values of a are issued
-// together, then:
+// WPW consecutive rows of T.  ta (a multiple of WPW, at most kPairTA) is
+// the number of a values per wave: the host takes fewer when the grid would
+// otherwise be too small to fill the chip.  The loads of WPW values of a
+// are issued together, then:
 //   M_a: each worker adds its b products in j order; the wave's workers
 //     then reduce-scatter the WPW rows (a butterfly that halves the rows
 //     each lane keeps at every step: worker w ends with the sum of row w),
@@ -243,7 +245,7 @@ constexpr int kPairTB = 16;
 template <int WPW>
 __global__ __launch_bounds__(kThreads) void k_pair_leaf(const float *__restrict__ Tm, int64_t A, int64_t B,
                                                         const float *__restrict__ Ua,
-                                                        const float *__restrict__ Ub, int R,
+                                                        const float *__restrict__ Ub, int R, int ta,
                                                         float *__restrict__ PA, float *__restrict__ PB) {
     constexpr int RC = 64 / WPW;
     constexpr int KB = kPairTB / WPW;
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_leaf(const float *__restrict_
     const bool col_ok = c4 < R;
     const int cc = col_ok ? c4 : 0;
     const int64_t b0 = (int64_t)blockIdx.x * kPairTB;
-    const int64_t a0 = (int64_t)blockIdx.y * (4 * kPairTA) + wave * kPairTA;
+    const int64_t a0 = (int64_t)blockIdx.y * (4 * ta) + wave * ta;
     const f32x4 zeros = {0.f, 0.f, 0.f, 0.f};
     // T and U_a through buffer resources: a lane offset plus a wave-uniform
     // row offset.  The host keeps every offset of T below 2^32; lanes past B
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_leaf(const float *__restrict_
         for (int e = 0; e < 4; ++e) accb[j][e] = 0.0;
     // one chunk of loads in flight per wave: the resident waves overlap them
 #pragma unroll 1
-    for (int ac = 0; ac < kPairTA; ac += WPW) {
+    for (int ac = 0; ac < ta; ac += WPW) {
         f32x4 v[WPW][KB];
 #pragma unroll
         for (int u = 0; u < WPW; ++u) {
