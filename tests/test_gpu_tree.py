@@ -1,6 +1,7 @@
 """GPU parity of the all-mode MTTKRP with cross-mode reuse (mttkrp_all), and
-of cp_grad / cp_als_step, which form their MTTKRPs the same way from N = 4
-on, against the FP64 oracle.
+of cp_grad / cp_als_step, which form their MTTKRPs the same way (from N = 4
+on, and for 3-way tensors whose wide pass qualifies), against the FP64
+oracle.
 
 The reuse changes only the order of the sums (one group's modes contracted
 first, into an intermediate), so every mode must still meet the plain
