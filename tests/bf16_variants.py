@@ -36,6 +36,10 @@ VARIANT_CASES = [
     ((200, 3), 70, 1, "k_contract_left_bf16<NB=8,MB=1,Q=1,V8=1,WM=1>"),
     ((64, 48, 80), 70, 1, "k_contract_left_bf16<NB=8,MB=1,Q=1,V8=1,WM=2>"),
     ((64, 48, 80), 70, 2, "k_contract_left_bf16<NB=8,MB=1,Q=1,V8=1,WM=4>"),
+    ((260, 40, 20), 70, 1, "k_contract_left_bf16<NB=8,MB=1,Q=2,V8=0,WM=2>"),
+    ((260, 70, 20), 70, 1, "k_contract_left_bf16<NB=8,MB=1,Q=2,V8=0,WM=4>"),
+    ((256, 40, 20), 70, 1, "k_contract_left_bf16<NB=8,MB=1,Q=2,V8=1,WM=2>"),
+    ((256, 70, 20), 70, 1, "k_contract_left_bf16<NB=8,MB=1,Q=2,V8=1,WM=4>"),
     ((37, 29, 41), 1, 0, "k_contract_right_bf16<NB=1,V8=0>"),
     ((64, 48, 80), 1, 0, "k_contract_right_bf16<NB=1,V8=1>"),
     ((37, 29, 41), 32, 0, "k_contract_right_bf16<NB=2,V8=0>"),
