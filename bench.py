@@ -287,6 +287,15 @@ def main():
             "step_components_us": {name: round(us, 2) for name, _, us, _, _ in launches},
             "ms_per_step_three_single_mode_calls": round(sum(per_mode), 4),
             "wall_s_timed": round(wall, 3)}
+    # context for the fraction above: what PyTorch's own streaming kernels
+    # reach on the same 512 MiB tensor on this GPU (a reduction reads it
+    # once; a copy reads and writes it)
+    dst = torch.empty_like(X)
+    t_sum = timed(torch, stream, lambda: X.sum(), args.steps)
+    t_copy = timed(torch, stream, lambda: dst.copy_(X), args.steps)
+    line["read_probe"] = {"torch_sum_GB/s": round(I * 4 / (t_sum / 1e3) / 1e9, 1),
+                          "torch_copy_GB/s": round(2 * I * 4 / (t_copy / 1e3) / 1e9, 1)}
+    del dst
     rooflines = [dict(roofline, workload="512^3 float32 R=32, slowest pass of the step")]
 
     if not args.quick:
