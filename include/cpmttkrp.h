@@ -279,7 +279,8 @@ size_t cpm_cp_grad_workspace_bytes(const int64_t *dims, int N, int R, cpm_dtype 
  * or negative to have it computed (only needed when fit_out is non-null).
  * fit_out: host pointer, may be null; receives 1 - ||X - Y|| / ||X|| of the
  * updated model (from ||X||^2 - 2 <M_{N-1}, U_{N-1}> + sum(Hadamard of all
- * Grams), accumulated in float64).  Waits for the stream once.
+ * Grams), accumulated in float64).  Waits for the stream once (and once
+ * more to restore the factors when it fails).
  * Where `mttkrp_all` would split the modes, the MTTKRPs come from its two
  * passes: the
  * left group's intermediate depends only on factors not yet updated when

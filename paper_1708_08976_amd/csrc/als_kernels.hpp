@@ -106,12 +106,19 @@ __global__ __launch_bounds__(kThreads) void k_hadamard_except(const double *__re
 // (row-major, zero above the diagonal) and its transpose Lt.  If a pivot is
 // not positive the factorisation stops and *status is set to 1 (it is never
 // cleared here, so one failure in a sweep is remembered).
-__global__ __launch_bounds__(kThreads) void k_cholesky(const double *__restrict__ H, int R,
+// H itself is formed on the way into LDS: the Hadamard product of grams[k]
+// (N matrices of R x R) over k != skip.
+__global__ __launch_bounds__(kThreads) void k_cholesky(const double *__restrict__ grams, int N, int skip, int R,
                                                        double *__restrict__ L, double *__restrict__ Lt,
                                                        int *__restrict__ status) {
     extern __shared__ double A[];  // R x R
     const int t = threadIdx.x, ti = t >> 4, tk = t & 15;
-    for (int e = t; e < R * R; e += kThreads) A[e] = H[e];
+    for (int e = t; e < R * R; e += kThreads) {
+        double v = 1.0;
+        for (int k = 0; k < N; ++k)
+            if (k != skip) v *= grams[(int64_t)k * R * R + e];
+        A[e] = v;
+    }
     __syncthreads();
     for (int j = 0; j < R; ++j) {
         const double d = A[j * R + j];
@@ -186,16 +193,6 @@ __global__ __launch_bounds__(kThreads) void k_chol_solve_rows(const double *__re
         if (k0 < R) out[row * R + k0] = (T)v0;
         if (k1 < R) out[row * R + k1] = (T)v1;
     }
-}
-
-// Restore every factor from its snapshot when *status is set.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_restore_if_failed(const int *__restrict__ status,
-                                                                const T *__restrict__ snap, int64_t count,
-                                                                T *__restrict__ dst) {
-    if (!*status) return;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < count; e += (int64_t)gridDim.x * kThreads)
-        dst[e] = snap[e];
 }
 
 // grad[i][c] = sum_d U[i][d] H[d][c] - M[i][c], in float64.  A work-group

@@ -1952,12 +1952,11 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
             s = run_mttkrp(p, X, dims, N, cf, R, n, w.M, dt, w.all.mws, stream);
         }
         if (s) return s;
-        s = hadamard_except(w.grams, N, R, n, w.H, stream);
-        if (s) return s;
         if (n == 0 && lds_chol > 65536)
             HIP_TRY(hipFuncSetAttribute((const void *)k_cholesky, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)lds_chol));
-        hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kThreads), lds_chol, stream, w.H, R, w.L, w.Lt, w.status);
+        hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kThreads), lds_chol, stream, w.grams, N, n, R, w.L, w.Lt,
+                           w.status);
         LAUNCH_CHECK("k_cholesky");
         // L and L^T go to LDS when they fit 64 KB (R <= 64); one row per wave.
         const bool lds_l = R <= 64;
@@ -1996,25 +1995,23 @@ cpm_status cp_als_step(const void *X, const int64_t *dims, int N, void *const *f
         s = loss_enqueue(w.xnorm2, w.inner, w.grams, N, R, w.hpart, 1, w.result, stream);
         if (s) return s;
     }
-    off = 0;
-    for (int k = 0; k < N; ++k) {
-        const int64_t cnt = dims[k] * R;
-        const unsigned blocks = (unsigned)std::min<int64_t>(1024, ceil_div(cnt, kThreads));
-        if (dt == CPM_F64)
-            hipLaunchKernelGGL(k_restore_if_failed<double>, dim3(blocks), dim3(kThreads), 0, stream, w.status,
-                               (const double *)((char *)w.snap + off), cnt, (double *)factors[k]);
-        else
-            hipLaunchKernelGGL(k_restore_if_failed<float>, dim3(blocks), dim3(kThreads), 0, stream, w.status,
-                               (const float *)((char *)w.snap + off), cnt, (float *)factors[k]);
-        LAUNCH_CHECK("k_restore_if_failed");
-        off += (size_t)cnt * fz;
-    }
     int status_h = 0;
     double result_h = 0.0;
     HIP_TRY(hipMemcpyAsync(&status_h, w.status, sizeof(int), hipMemcpyDeviceToHost, stream));
     if (fit_out) HIP_TRY(hipMemcpyAsync(&result_h, w.result, sizeof(double), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    if (status_h) return fail(CPM_ENOTPD, "Hadamard product of Grams is not positive definite; factors restored");
+    if (status_h) {
+        // the modes before the failing one were updated: every factor goes
+        // back to its snapshot (only on this path, after the status is known)
+        off = 0;
+        for (int k = 0; k < N; ++k) {
+            const size_t bytes = (size_t)dims[k] * R * fz;
+            HIP_TRY(hipMemcpyAsync(factors[k], (char *)w.snap + off, bytes, hipMemcpyDeviceToDevice, stream));
+            off += bytes;
+        }
+        HIP_TRY(hipStreamSynchronize(stream));
+        return fail(CPM_ENOTPD, "Hadamard product of Grams is not positive definite; factors restored");
+    }
     if (fit_out) *fit_out = result_h;
     return CPM_OK;
 }
