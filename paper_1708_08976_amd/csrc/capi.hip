@@ -283,7 +283,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         // work-group (its j tile x R) stays small next to the X it streams.
         int tj = 1;
         if (p.NB == 1 && a4 && p.J >= 128) tj = 4;
-        else if (a2 && p.J >= 64) tj = 2;
+        else if (a2 && p.J >= 32) tj = 2;  // mode 0 of 60^5 (J = 60): 1.09 -> 0.75 ms against TJ = 1
         // A wide output (the cross-mode reuse's pass over a long left
         // product): each wave takes its own j range and streams the whole
         // contracted range, so the work-group needs no cross-wave reduction

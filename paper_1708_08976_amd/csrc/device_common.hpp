@@ -125,11 +125,15 @@ constexpr uint32_t kNoLoad = 0xFFFFFFF0u;
 // dword 3 of the resource: 32-bit data format, raw (untyped) access
 constexpr int kRsrcWord3 = 0x00020000;
 
-// Cache policy of the tensor's loads: bit 1 of a buffer load's policy
-// operand is the non-temporal hint.  A float32 tensor is read once per
-// pass, so its loads carry it and leave the caches to factor rows and
-// tiles.  On MI355X a plain 512 MiB read ran at about 6.0 TB/s without the
-// hint and 6.9 TB/s with it (the split-bf16 planes are read without it).
+// Cache policy of a buffer load: bit 1 of the policy operand is the
+// non-temporal hint.  On MI355X a plain 512 MiB read in 16-byte loads ran at
+// about 6.0 TB/s without it and 6.9 TB/s with it.  It is set where it
+// measured faster: the 16- and 8-byte tensor loads of the float32
+// right-first kernel (the 512^3 passes 7-14% faster) and the fused
+// residual's tensor loads (141 -> 131 us at 512^3).  The left-first kernels
+// (128-byte row segments in 16-byte loads), the 4-byte loads of rows that
+// are not 16-byte aligned and the split-bf16 planes were as fast or slower
+// with it (down to half the rate on 225 x 59 x 200 x 200).
 constexpr int kStream = 2;
 
 __device__ inline rsrc_t make_rsrc(const void *base, uint32_t bytes) {

@@ -111,10 +111,10 @@ __global__ __launch_bounds__(kThreads) void k_left32(const float *__restrict__ X
         for (int i = 0; i < 4; ++i) {
             const uint32_t off = loff[i] + (uint32_t)(WS * ls * 4);
             if constexpr (!PART) {
-                a[i] = buf_load4<kStream>(rs, (!ragged || e0 < lcount) ? off : kNoLoad, 0.f);
+                a[i] = buf_load4(rs, (!ragged || e0 < lcount) ? off : kNoLoad, 0.f);
             } else {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) a[i][t] = buf_load1<kStream>(rs, e0 + t < lcount ? off + 4 * t : kNoLoad, 0.f);
+                for (int t = 0; t < 4; ++t) a[i][t] = buf_load1(rs, e0 + t < lcount ? off + 4 * t : kNoLoad, 0.f);
             }
         }
         if (++ls == SPB) {
@@ -244,7 +244,7 @@ __device__ inline typename JVec<TJ>::type buf_loadj(rsrc_t r, uint32_t off) {
     if constexpr (TJ == 4) return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kStream));
     else if constexpr (TJ == 2)
         return __builtin_bit_cast(typename JVec<2>::type, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kStream));
-    else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kStream));
+    else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 template <int TJ>
 __device__ inline float jcomp(const typename JVec<TJ>::type &v, int t) {
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void k_right32(const float *__restrict__ 
             } else {
 #pragma unroll
                 for (int t = 0; t < TJ; ++t)
-                    jset<TJ>(a[s], t, buf_load1<kStream>(rs, jw + TJ * m + t < J ? off + 4 * t : kNoLoad, 0.f));
+                    jset<TJ>(a[s], t, buf_load1(rs, jw + TJ * m + t < J ? off + 4 * t : kNoLoad, 0.f));
             }
         }
         if (++ls == SPB) {

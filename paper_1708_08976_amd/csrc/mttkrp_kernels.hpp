@@ -164,14 +164,14 @@ __global__ __launch_bounds__(kThreads) void k_contract_left(
                 if (V4) {
                     const bool ok = live && rok[mb] && l < lend;
                     const uint32_t off = ok ? (uint32_t)((lane_row + l) * sizeof(T)) : kNoLoad;
-                    const acc_t v = buf_load4<kStream>(rs[mb], off, T(0));
+                    const acc_t v = buf_load4(rs[mb], off, T(0));
                     a[mb][q][0] = v[0]; a[mb][q][1] = v[1]; a[mb][q][2] = v[2]; a[mb][q][3] = v[3];
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const bool ok = live && rok[mb] && l + e < lend;
                         const uint32_t off = ok ? (uint32_t)((lane_row + l + e) * sizeof(T)) : kNoLoad;
-                        a[mb][q][e] = buf_load1<kStream>(rs[mb], off, T(0));
+                        a[mb][q][e] = buf_load1(rs[mb], off, T(0));
                     }
                 }
             }
@@ -354,14 +354,14 @@ __global__ __launch_bounds__(kThreads) void k_contract_right(
                 if (V4) {
                     const bool ok = rok && jok[g];
                     const uint32_t off = ok ? (uint32_t)((rl * J + jl) * sizeof(T)) : kNoLoad;
-                    const acc_t v = buf_load4<kStream>(rs, off, T(0));
+                    const acc_t v = buf_load4(rs, off, T(0));
                     a[t][g][0] = v[0]; a[t][g][1] = v[1]; a[t][g][2] = v[2]; a[t][g][3] = v[3];
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const bool ok = rok && jj[g] + e < J;
                         const uint32_t off = ok ? (uint32_t)((rl * J + jl + e) * sizeof(T)) : kNoLoad;
-                        a[t][g][e] = buf_load1<kStream>(rs, off, T(0));
+                        a[t][g][e] = buf_load1(rs, off, T(0));
                     }
                 }
             }

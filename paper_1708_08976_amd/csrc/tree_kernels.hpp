@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_leaf(const float *__restrict_
             for (int j = 0; j < KB; ++j) {
                 const uint32_t row_off = (uint32_t)(((a * B) + b0 + WPW * j) * R * 4);
                 const f32x4 x = __builtin_bit_cast(
-                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(rt, lane_off, (int)row_off, kStream));
+                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(rt, lane_off, (int)row_off, 0));
                 v[u][j] = (a < A && bok[j]) ? x : zeros;
             }
         }
