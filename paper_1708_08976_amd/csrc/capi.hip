@@ -1073,12 +1073,15 @@ cpm_status tree_pair_leaf(const TreePlan &t, const int64_t *dims, const void *co
         if ((uintptr_t)p % 16 != 0) return CPM_OK;
     const dim3 grid((unsigned)q.gx, (unsigned)q.gy);
     const float *Ub = (const float *)factors[g0], *Ua = (const float *)factors[g0 + 1];
-    if (q.wpw == 8)
-        hipLaunchKernelGGL(k_pair_leaf<8>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, q.ta, PA, PB);
-    else if (q.wpw == 4)
-        hipLaunchKernelGGL(k_pair_leaf<4>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, q.ta, PA, PB);
-    else
-        hipLaunchKernelGGL(k_pair_leaf<2>, grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, q.ta, PA, PB);
+#define PAIR_LEAF(W, T) \
+    hipLaunchKernelGGL((k_pair_leaf<W, T>), grid, dim3(kThreads), 0, st, Tm, A, B, Ua, Ub, R, PA, PB)
+    if (q.wpw == 8) PAIR_LEAF(8, 8);
+    else if (q.wpw == 4 && q.ta == 8) PAIR_LEAF(4, 8);
+    else if (q.wpw == 4) PAIR_LEAF(4, 4);
+    else if (q.ta == 8) PAIR_LEAF(2, 8);
+    else if (q.ta == 4) PAIR_LEAF(2, 4);
+    else PAIR_LEAF(2, 2);
+#undef PAIR_LEAF
     LAUNCH_CHECK("k_pair_leaf");
     const int64_t blocks_a = q.bytes_a ? ceil_div(A * R, 64) : 0;
     const int64_t blocks_b = q.bytes_b ? ceil_div(B * R, 64) : 0;
