@@ -175,11 +175,7 @@ size_t cpm_mttkrp_all_workspace_bytes(const int64_t *dims, int N, int R, cpm_dty
  * `cpm_mttkrp_all_workspace_bytes` reserves room for it exactly then).
  * Otherwise (and for N = 2) each mode is an ordinary `mttkrp`.  The result
  * agrees with `mttkrp` to rounding (a different summation order) and is
- * bitwise reproducible run to run.  Stream-ordered, no synchronisation: the
- * leaf work of the first group may run on a second stream the library keeps
- * per device, forked from and joined back into `stream` with events, so
- * everything the call enqueues is complete when `stream` reaches the end of
- * the call.
+ * bitwise reproducible run to run.  Stream-ordered, no synchronisation.
  */
 cpm_status mttkrp_all(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
                       void *const *outs, cpm_dtype dt, void *workspace, size_t ws_bytes,
