@@ -1095,60 +1095,6 @@ cpm_status tree_pair_leaf(const TreePlan &t, const int64_t *dims, const void *co
     return CPM_OK;
 }
 
-// A second stream per device for work that may run beside the caller's
-// stream (created once, default priority, kept until the process ends), and
-// a fork/join of it around a stretch of the caller's stream: begin() makes
-// the side stream wait for everything the caller's stream has enqueued so
-// far, end() makes the caller's stream wait for everything enqueued on the
-// side stream since.  The events are made per fork, so calls from several
-// host threads never wait on each other's points.  Both steps are stream
-// operations only (no host wait), so the sequence can be captured.
-constexpr int kMaxDevices = 64;
-std::mutex g_side_mu;
-hipStream_t g_side[kMaxDevices];
-
-struct SideFork {
-    hipStream_t side = nullptr, main_st = nullptr;
-    hipEvent_t join = nullptr;
-    cpm_status begin(hipStream_t st) {
-        main_st = st;
-        int dev = 0;
-        HIP_TRY(hipGetDevice(&dev));
-        if (dev < 0 || dev >= kMaxDevices) return fail(CPM_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
-        {
-            std::lock_guard<std::mutex> lock(g_side_mu);
-            if (!g_side[dev]) HIP_TRY(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
-            side = g_side[dev];
-        }
-        hipEvent_t fork = nullptr;
-        HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-        hipError_t e = hipEventRecord(fork, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
-        hipEventDestroy(fork);
-        if (e != hipSuccess) {
-            side = nullptr;
-            return fail(CPM_EHIP, "side stream fork: %s", hipGetErrorString(e));
-        }
-        return CPM_OK;
-    }
-    cpm_status end(hipStream_t st) {
-        if (!side) return CPM_OK;
-        HIP_TRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
-        hipError_t e = hipEventRecord(join, side);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
-        hipEventDestroy(join);
-        join = nullptr;
-        side = nullptr;
-        if (e != hipSuccess) return fail(CPM_EHIP, "side stream join: %s", hipGetErrorString(e));
-        return CPM_OK;
-    }
-    ~SideFork() {
-        // an early return between begin() and end() leaves no dangling work
-        // behind the caller's stream: join it
-        if (side) end(main_st);
-    }
-};
-
 // Every requested mode's MTTKRP (arguments validated, workspace laid out):
 // the two-group reuse when it pays, otherwise one ordinary MTTKRP per mode.
 cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *const *factors, int R,
@@ -1165,10 +1111,6 @@ cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *co
     tree.use = tree.use && nwant >= 3 && w.TL && tree_reach_ok(tree, X, R, dt);
     bool done[CPM_MAX_MODES] = {};
     if (tree.use) {
-        auto pair_wanted = [&](int g0) {
-            const int g1 = g0 == 0 ? tree.s : N;
-            return g1 - g0 == 2 && outs[g0] && outs[g0 + 1] && dt != CPM_F64;
-        };
         // a one-mode group's intermediate is that mode's MTTKRP: its pass
         // writes the output directly
         if (want_left) {
@@ -1177,30 +1119,17 @@ cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *co
             if (s) return s;
             done[0] = one;
         }
-        // The left group's pair leaf needs only pass A: it runs on a side
-        // stream beside pass B, joined before anything else uses the leaf
-        // workspace.
-        SideFork fork;
-        if (want_left && want_right && pair_wanted(0)) {
-            s = fork.begin(stream);
-            if (s) return s;
-            bool pair = false;
-            s = tree_pair_leaf(tree, dims, factors, R, 0, dt, w, outs[0], outs[1], fork.side, &pair);
-            if (s) return s;
-            done[0] = done[1] = pair;
-        }
         if (want_right) {
             const bool one = tree_single(tree, N, N - 1);
             s = tree_pass(tree, false, X, factors, R, dt, w, stream, one ? outs[N - 1] : nullptr);
             if (s) return s;
             done[N - 1] = one;
         }
-        s = fork.end(stream);
-        if (s) return s;
         // a two-mode group with both modes wanted: one pass over its
         // intermediate for both
         for (int g0 : {0, tree.s}) {
-            if (!pair_wanted(g0) || done[g0]) continue;
+            const int g1 = g0 == 0 ? tree.s : N;
+            if (g1 - g0 != 2 || !outs[g0] || !outs[g0 + 1] || dt == CPM_F64) continue;
             bool pair = false;
             s = tree_pair_leaf(tree, dims, factors, R, g0, dt, w, outs[g0], outs[g0 + 1], stream, &pair);
             if (s) return s;
@@ -1627,6 +1556,7 @@ cpm_status check_lds_for_cholesky(int R) {
 
 // Device address of `scratch` on the current device, looked up once per
 // device (with that device current) and cached.
+constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[kMaxDevices];
 
