@@ -169,22 +169,27 @@ __global__ __launch_bounds__(kThreads) void k_chol_solve_rows(const double *__re
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int k0 = lane, k1 = lane + 64;
+    // each lane holds the reciprocal pivots of its own entries, so step j
+    // takes lane j's value already divided: one multiply and one shuffle on
+    // the dependent chain instead of a float64 division and an LDS read
+    const double r0 = (k0 < R) ? 1.0 / L[k0 * R + k0] : 0.0;
+    const double r1 = (k1 < R) ? 1.0 / L[k1 * R + k1] : 0.0;
     for (int rr = 0; rr < rows_per_wave; ++rr) {
         const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * rows_per_wave + rr;
         if (row >= In) break;
         double v0 = (k0 < R) ? (double)M[row * R + k0] : 0.0;
         double v1 = (k1 < R) ? (double)M[row * R + k1] : 0.0;
         for (int j = 0; j < R; ++j) {  // forward: column j of L is row j of Lt
-            const double src = (j < 64) ? v0 : v1;
-            const double yj = __shfl(src, j & 63) / L[j * R + j];
+            const double src = (j < 64) ? v0 * r0 : v1 * r1;
+            const double yj = __shfl(src, j & 63);
             if (j < 64) { if (lane == j) v0 = yj; } else { if (lane == j - 64) v1 = yj; }
             const double *col = Lt + (int64_t)j * R;
             if (k0 > j && k0 < R) v0 -= col[k0] * yj;
             if (k1 > j && k1 < R) v1 -= col[k1] * yj;
         }
         for (int j = R - 1; j >= 0; --j) {  // backward: column j of L^T is row j of L
-            const double src = (j < 64) ? v0 : v1;
-            const double xj = __shfl(src, j & 63) / L[j * R + j];
+            const double src = (j < 64) ? v0 * r0 : v1 * r1;
+            const double xj = __shfl(src, j & 63);
             if (j < 64) { if (lane == j) v0 = xj; } else { if (lane == j - 64) v1 = xj; }
             const double *rowL = L + (int64_t)j * R;
             if (k0 < j) v0 -= rowL[k0] * xj;
