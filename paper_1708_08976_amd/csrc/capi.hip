@@ -130,6 +130,17 @@ struct Plan {
 constexpr int kTargetGroups = 512;        // about two resident work-groups per CU
 constexpr size_t kTileBytes = 78 * 1024;   // LDS for the resident Khatri-Rao tile
 
+// Splits the outer blocks so the grid holds at most `groups` work-groups
+// (one round of resident work-groups): rounding the split count up instead
+// put a grid just past a round (516 for 512 slots) in two rounds of the
+// same length.
+void split_outer(Plan &p, int64_t groups) {
+    int64_t S = std::max<int64_t>(1, groups / (p.ntiles * p.nlc * p.ncb));
+    S = std::min(S, p.n_outer);
+    p.bps = ceil_div(p.n_outer, S);
+    p.S = ceil_div(p.n_outer, p.bps);
+}
+
 int pow2_at_least(int v) {
     int p = 1;
     while (p < v) p <<= 1;
@@ -204,7 +215,16 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
         if (q == mode + 1 && q < N) p.G_in = dims[q++];
         p.p = q;
         p.n_outer = p.IR / p.G_in;
-        p.LC = (int)std::min<int64_t>(lcmax, ceil_div(p.G_in, 32) * 32);
+        // Chunks of equal step counts, the count (up to twice the fewest)
+        // that pads the fewest steps: every block runs SPB steps whatever
+        // its chunk holds, so 256 rows in chunks of 96 ran 288 rows of steps
+        // (four chunks of 64: 256).
+        const int64_t g32 = ceil_div(p.G_in, 32);
+        const int64_t c0 = ceil_div(p.G_in, lcmax);
+        int64_t lc = ceil_div(g32, c0) * 32;
+        for (int64_t c = c0 + 1; c <= std::min(g32, 2 * c0); ++c)
+            if (c * ceil_div(g32, c) * 32 < ceil_div(p.G_in, lc) * lc) lc = ceil_div(g32, c) * 32;
+        p.LC = (int)lc;
         p.SPB = p.LC / 32;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.J, 64);
@@ -212,10 +232,7 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
         p.v4 = (p.J % 8 == 0) && (I % 8 == 0) && ((uintptr_t)X % 16 == 0);
         p.max_offset = ((int64_t)p.LC * p.J + 64 + 8) * 2;
     }
-    int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.nlc * p.ncb));
-    S = std::min(S, p.n_outer);
-    p.bps = ceil_div(p.n_outer, S);
-    p.S = ceil_div(p.n_outer, p.bps);
+    split_outer(p, kTargetGroups);
     p.reduce = p.S * p.nlc > 1 || (p.kind == kBf16Right && mode > 0);
     const int64_t rows = p.kind == kBf16Left ? p.In : p.J;
     p.partial_bytes = p.reduce ? (size_t)p.S * p.nlc * rows * R * 4 : 0;
@@ -324,10 +341,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.max_offset = ((int64_t)p.LC * p.J + 32 * tj + 4) * 4;
     }
     const int64_t groups = p.kind == kLeft32 ? kF32GroupsLeft : kF32GroupsRight;
-    int64_t S = std::max<int64_t>(1, ceil_div(groups, p.ntiles * p.nlc * p.ncb));
-    S = std::min(S, p.n_outer);
-    p.bps = ceil_div(p.n_outer, S);
-    p.S = ceil_div(p.n_outer, p.bps);
+    split_outer(p, groups);
     p.reduce = p.S * p.nlc > 1 || (p.kind == kRight32 && mode > 0);
     p.partial_bytes = p.reduce ? (size_t)p.S * p.nlc * (p.kind == kLeft32 ? p.In : p.J) * R * 4 : 0;
     return true;
@@ -406,10 +420,7 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
         p.ntiles = ceil_div(p.In, 16 * p.MB);
         const size_t red = (size_t)4 * p.MB * p.NB * 256 * sz;
         p.lds = std::max((size_t)p.LC * pitch * sz, red);
-        int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.nlc * p.ncb));
-        S = std::min(S, p.n_outer);
-        p.bps = ceil_div(p.n_outer, S);
-        p.S = ceil_div(p.n_outer, p.bps);
+        split_outer(p, kTargetGroups);
         p.v4 = (p.G_in % 4 == 0) && ((uintptr_t)X % (4 * sz) == 0);
         p.max_offset = (15 * p.IL + p.G_in + 4) * (int64_t)sz;  // lane offsets within one m-block
         p.J = p.In;
@@ -427,10 +438,7 @@ Plan make_plan(const int64_t *dims, int N, int R, int mode, cpm_dtype dt, const 
         p.ntiles = ceil_div(p.J, 64 * p.MB);
         const size_t red = (size_t)4 * p.MB * 4 * p.NB * 256 * sz;
         p.lds = std::max((size_t)p.LC * pitch * sz, red);
-        int64_t S = std::max<int64_t>(1, ceil_div(kTargetGroups, p.ntiles * p.nlc * p.ncb));
-        S = std::min(S, p.n_outer);
-        p.bps = ceil_div(p.n_outer, S);
-        p.S = ceil_div(p.n_outer, p.bps);
+        split_outer(p, kTargetGroups);
         p.v4 = (p.J % 4 == 0) && ((uintptr_t)X % (4 * sz) == 0);
         p.max_offset = ((16 * (int64_t)p.SPB) * p.J + 64 * p.MB + 4) * (int64_t)sz;  // within one wave's rows
         p.reduce = p.S * p.nlc > 1 || mode > 0;  // mode > 0: the multi-TTV with K_L runs in the reduction
