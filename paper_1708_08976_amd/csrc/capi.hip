@@ -243,8 +243,20 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
 // is grown until it reaches the chunk length (a long inner range is then cut
 // into chunks).  Returns false when these kernels do not apply.
 constexpr int64_t kF32Chunk = 128;  // inner entries per work-group (tile of 16 KB per 32 columns)
-constexpr int kF32GroupsLeft = 768;   // three resident work-groups per CU
-constexpr int kF32GroupsRight = 512;  // two (its cross-wave reduction takes 16 KB of LDS per j)
+constexpr int kF32GroupsRight = 512;  // wide-output test: j tiles that occupy every CU
+
+// Work-groups of a float32 contraction kernel resident on one CU: each has
+// one wave per SIMD, so the waves per SIMD its registers allow (from the
+// compiled kernels: k_left32 three at one 32-column block and two at more;
+// k_right32 four at one column block and one j per lane, three at two
+// columns-times-j, two at four), and what its LDS allows.
+int64_t f32_groups(const Plan &p) {
+    int regs;
+    if (p.kind == kLeft32) regs = p.NB == 1 ? 3 : 2;
+    else regs = p.NB * p.Q == 1 ? 4 : (p.NB * p.Q == 2 ? 3 : 2);
+    const int64_t lds = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)p.lds);
+    return 256 * std::min<int64_t>(regs, lds);
+}
 
 // tight: the inner contracted group grows only while it still fits one
 // chunk (at least one mode), so the contracted range is not cut into chunks
@@ -340,8 +352,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.v4 = tj > 1;
         p.max_offset = ((int64_t)p.LC * p.J + 32 * tj + 4) * 4;
     }
-    const int64_t groups = p.kind == kLeft32 ? kF32GroupsLeft : kF32GroupsRight;
-    split_outer(p, groups);
+    split_outer(p, f32_groups(p));
     p.reduce = p.S * p.nlc > 1 || (p.kind == kRight32 && mode > 0);
     p.partial_bytes = p.reduce ? (size_t)p.S * p.nlc * (p.kind == kLeft32 ? p.In : p.J) * R * 4 : 0;
     return true;
