@@ -1130,29 +1130,35 @@ cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *co
     tree.use = tree.use && nwant >= 3 && w.TL && tree_reach_ok(tree, X, R, dt);
     bool done[CPM_MAX_MODES] = {};
     if (tree.use) {
-        // a one-mode group's intermediate is that mode's MTTKRP: its pass
-        // writes the output directly
+        // A one-mode group's intermediate is that mode's MTTKRP: its pass
+        // writes the output directly.  A two-mode group with both modes
+        // wanted takes one pass over its intermediate for both, launched
+        // right after the pass that wrote it (the intermediate is then
+        // still in the last-level cache).
+        auto pair_of = [&](int g0) -> cpm_status {
+            const int g1 = g0 == 0 ? tree.s : N;
+            if (g1 - g0 != 2 || !outs[g0] || !outs[g0 + 1] || dt == CPM_F64) return CPM_OK;
+            bool pair = false;
+            const cpm_status r =
+                tree_pair_leaf(tree, dims, factors, R, g0, dt, w, outs[g0], outs[g0 + 1], stream, &pair);
+            done[g0] = done[g0 + 1] = pair;
+            return r;
+        };
         if (want_left) {
             const bool one = tree_single(tree, N, 0);
             s = tree_pass(tree, true, X, factors, R, dt, w, stream, one ? outs[0] : nullptr);
             if (s) return s;
             done[0] = one;
+            s = pair_of(0);
+            if (s) return s;
         }
         if (want_right) {
             const bool one = tree_single(tree, N, N - 1);
             s = tree_pass(tree, false, X, factors, R, dt, w, stream, one ? outs[N - 1] : nullptr);
             if (s) return s;
             done[N - 1] = one;
-        }
-        // a two-mode group with both modes wanted: one pass over its
-        // intermediate for both
-        for (int g0 : {0, tree.s}) {
-            const int g1 = g0 == 0 ? tree.s : N;
-            if (g1 - g0 != 2 || !outs[g0] || !outs[g0 + 1] || dt == CPM_F64) continue;
-            bool pair = false;
-            s = tree_pair_leaf(tree, dims, factors, R, g0, dt, w, outs[g0], outs[g0 + 1], stream, &pair);
+            s = pair_of(tree.s);
             if (s) return s;
-            done[g0] = done[g0 + 1] = pair;
         }
     }
     for (int n = 0; n < N; ++n) {
