@@ -141,6 +141,20 @@ void split_outer(Plan &p, int64_t groups) {
     p.S = ceil_div(p.n_outer, p.bps);
 }
 
+// Chunk length (a multiple of unit, at most lcmax) for an inner range of
+// G rows: chunks of equal step counts, the count (up to twice the fewest)
+// that pads the fewest steps.  Every block runs a chunk's worth of steps
+// whatever the chunk holds, so 256 rows in chunks of 96 ran 288 rows of
+// steps, and four chunks of 64 run 256.
+int even_chunk(int64_t G, int64_t lcmax, int64_t unit) {
+    const int64_t g = ceil_div(G, unit);
+    const int64_t c0 = ceil_div(G, lcmax);
+    int64_t lc = ceil_div(g, c0) * unit;
+    for (int64_t c = c0 + 1; c <= std::min(g, 2 * c0); ++c)
+        if (c * ceil_div(g, c) * unit < ceil_div(G, lc) * lc) lc = ceil_div(g, c) * unit;
+    return (int)lc;
+}
+
 int pow2_at_least(int v) {
     int p = 1;
     while (p < v) p <<= 1;
@@ -215,16 +229,7 @@ void plan_bf16(Plan &p, const int64_t *dims, int N, int R, int mode, const void 
         if (q == mode + 1 && q < N) p.G_in = dims[q++];
         p.p = q;
         p.n_outer = p.IR / p.G_in;
-        // Chunks of equal step counts, the count (up to twice the fewest)
-        // that pads the fewest steps: every block runs SPB steps whatever
-        // its chunk holds, so 256 rows in chunks of 96 ran 288 rows of steps
-        // (four chunks of 64: 256).
-        const int64_t g32 = ceil_div(p.G_in, 32);
-        const int64_t c0 = ceil_div(p.G_in, lcmax);
-        int64_t lc = ceil_div(g32, c0) * 32;
-        for (int64_t c = c0 + 1; c <= std::min(g32, 2 * c0); ++c)
-            if (c * ceil_div(g32, c) * 32 < ceil_div(p.G_in, lc) * lc) lc = ceil_div(g32, c) * 32;
-        p.LC = (int)lc;
+        p.LC = even_chunk(p.G_in, lcmax, 32);
         p.SPB = p.LC / 32;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.J, 64);
@@ -343,7 +348,7 @@ bool plan_f32(Plan &p, const int64_t *dims, int N, int R, int mode, const void *
         p.p = q;
         p.n_outer = p.IR / p.G_in;
         const int64_t lcmax = std::max<int64_t>(unit, lcap / unit * unit);
-        p.LC = (int)std::min<int64_t>(lcmax, ceil_div(p.G_in, unit) * unit);
+        p.LC = even_chunk(p.G_in, lcmax, unit);
         p.SPB = p.LC / (int)unit;
         p.nlc = ceil_div(p.G_in, p.LC);
         p.ntiles = ceil_div(p.J, 32 * tj * wj);
