@@ -600,10 +600,40 @@ Krp<T> krp_of(const void *const *factors, const int64_t *dims, const int *modes,
     return k;
 }
 
+// Slice sums queued for one k_sum_jobs launch.  A caller queues only sums
+// whose slices stay untouched until the flush, and flushes before anything
+// reads their outputs.
+struct SumList {
+    SumJobs j{};
+};
+
+cpm_status sum_flush(SumList &L, hipStream_t st) {
+    if (L.j.count == 0) return CPM_OK;
+    const int64_t blocks = L.j.first[L.j.count];
+    hipLaunchKernelGGL(k_sum_jobs, dim3((unsigned)blocks), dim3(kThreads), 0, st, L.j);
+    L.j = SumJobs{};
+    LAUNCH_CHECK("k_sum_jobs");
+    return CPM_OK;
+}
+
+cpm_status sum_add(SumList &L, const float *P, int64_t S, int64_t n, float *M, hipStream_t st) {
+    if (L.j.count == kSumJobs) {
+        const cpm_status s = sum_flush(L, st);
+        if (s) return s;
+    }
+    const int k = L.j.count++;
+    L.j.P[k] = P;
+    L.j.M[k] = M;
+    L.j.S[k] = S;
+    L.j.n[k] = n;
+    L.j.first[k + 1] = L.j.first[k] + ceil_div(n, 64);
+    return CPM_OK;
+}
+
 // Enqueue one MTTKRP (arguments already validated).
 template <typename T>
 cpm_status run_mttkrp_t(const Plan &p, const void *Xv, const int64_t *dims, int N, const void *const *factors,
-                        int R, int mode, void *outv, void *ws, hipStream_t st) {
+                        int R, int mode, void *outv, void *ws, hipStream_t st, SumList *defer = nullptr) {
     int in_modes[CPM_MAX_MODES], out_modes[CPM_MAX_MODES], left_modes[CPM_MAX_MODES];
     int nin = 0, nout = 0, nleft = 0;
     for (int k = 0; k < mode; ++k) left_modes[nleft++] = k;
@@ -636,6 +666,11 @@ cpm_status run_mttkrp_t(const Plan &p, const void *Xv, const int64_t *dims, int 
     } else if (p.kind == kRight) {
         launch_right<T>(p, X, kin, kout, R, partial, st);
         LAUNCH_CHECK("k_contract_right");
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        // left-first partials are plain slices of the output: the caller
+        // may add them in a later k_sum_jobs launch (the same sums)
+        if (p.reduce && lf && defer) return sum_add(*defer, partial, p.S * p.nlc, p.In * R, out, st);
     }
     if (p.reduce) {
         const int64_t total = p.In * R;
@@ -775,8 +810,9 @@ cpm_status run_mttkrp_bf16(const Plan &p, const void *Xv, const int64_t *dims, i
 }
 
 cpm_status run_mttkrp(const Plan &p, const void *X, const int64_t *dims, int N, const void *const *factors,
-                      int R, int mode, void *out, cpm_dtype dt, void *ws, hipStream_t st) {
-    if (dt == CPM_F32) return run_mttkrp_t<float>(p, X, dims, N, factors, R, mode, out, ws, st);
+                      int R, int mode, void *out, cpm_dtype dt, void *ws, hipStream_t st,
+                      SumList *defer = nullptr) {
+    if (dt == CPM_F32) return run_mttkrp_t<float>(p, X, dims, N, factors, R, mode, out, ws, st, defer);
     if (dt == CPM_F64) return run_mttkrp_t<double>(p, X, dims, N, factors, R, mode, out, ws, st);
     return run_mttkrp_bf16(p, X, dims, N, factors, R, mode, out, ws, st);
 }
@@ -1015,19 +1051,19 @@ AllWs layout_all(const int64_t *dims, int N, int R, cpm_dtype dt, char *base, si
 // dst, when non-null, receives the intermediate instead of the workspace
 // (a one-mode group's intermediate is that mode's MTTKRP).
 cpm_status tree_pass(const TreePlan &t, bool left, const void *X, const void *const *factors, int R, cpm_dtype dt,
-                     const AllWs &w, hipStream_t st, void *dst = nullptr) {
+                     const AllWs &w, hipStream_t st, void *dst = nullptr, SumList *defer = nullptr) {
     const void *f[CPM_MAX_MODES];
     if (left) {
         const int N = t.nA + t.s - 1;
         f[0] = nullptr;
         for (int k = t.s; k < N; ++k) f[k - t.s + 1] = factors[k];
         const Plan p = make_plan(t.dA, t.nA, R, 0, dt, X);
-        return run_mttkrp(p, X, t.dA, t.nA, f, R, 0, dst ? dst : w.TL, dt, w.mws, st);
+        return run_mttkrp(p, X, t.dA, t.nA, f, R, 0, dst ? dst : w.TL, dt, w.mws, st, defer);
     }
     for (int k = 0; k < t.s; ++k) f[k] = factors[k];
     f[t.s] = nullptr;
     const Plan p = make_plan(t.dB, t.nB, R, t.s, dt, X);
-    return run_mttkrp(p, X, t.dB, t.nB, f, R, t.s, dst ? dst : w.TR, dt, w.mws, st);
+    return run_mttkrp(p, X, t.dB, t.nB, f, R, t.s, dst ? dst : w.TR, dt, w.mws, st, defer);
 }
 
 template <typename T>
@@ -1085,7 +1121,7 @@ bool tree_single(const TreePlan &t, int N, int n) { return n < t.s ? t.s == 1 : 
 // allow it (the caller then runs the two single-mode leaves).
 cpm_status tree_pair_leaf(const TreePlan &t, const int64_t *dims, const void *const *factors, int R, int g0,
                           cpm_dtype dt, const AllWs &w, void *out_fast, void *out_slow, hipStream_t st,
-                          bool *done) {
+                          bool *done, SumList *defer = nullptr) {
     *done = false;
     const int64_t B = dims[g0], A = dims[g0 + 1];
     const PairShape q = pair_shape(B, A, R, dt);
@@ -1107,14 +1143,14 @@ cpm_status tree_pair_leaf(const TreePlan &t, const int64_t *dims, const void *co
     else PAIR_LEAF(2, 2);
 #undef PAIR_LEAF
     LAUNCH_CHECK("k_pair_leaf");
-    const int64_t blocks_a = q.bytes_a ? ceil_div(A * R, 64) : 0;
-    const int64_t blocks_b = q.bytes_b ? ceil_div(B * R, 64) : 0;
-    if (blocks_a + blocks_b > 0) {
-        hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)(blocks_a + blocks_b)), dim3(kThreads), 0, st, PA,
-                           q.bytes_a ? q.gx : (int64_t)0, A, (float *)out_slow, PB, q.bytes_b ? q.gy : (int64_t)0,
-                           B, (float *)out_fast, R, blocks_a);
-        LAUNCH_CHECK("k_pair_reduce");
-    }
+    // the slice sums: queued on the caller's list, or launched here
+    SumList local;
+    SumList &L = defer ? *defer : local;
+    cpm_status s = CPM_OK;
+    if (q.bytes_a) s = sum_add(L, PA, q.gx, A * R, (float *)out_slow, st);
+    if (!s && q.bytes_b) s = sum_add(L, PB, q.gy, B * R, (float *)out_fast, st);
+    if (!s && !defer) s = sum_flush(L, st);
+    if (s) return s;
     *done = true;
     return CPM_OK;
 }
@@ -1140,12 +1176,18 @@ cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *co
         // wanted takes one pass over its intermediate for both, launched
         // right after the pass that wrote it (the intermediate is then
         // still in the last-level cache).
+        // When the right group is one mode, the left pair's slice sums wait
+        // for the right pass and go out with its split-K sums in one launch
+        // (the pair's slices sit in the leaf workspace, which that pass does
+        // not touch); otherwise each list is launched where it is filled.
+        const bool merge = want_right && tree_single(tree, N, N - 1);
+        SumList sums;
         auto pair_of = [&](int g0) -> cpm_status {
             const int g1 = g0 == 0 ? tree.s : N;
             if (g1 - g0 != 2 || !outs[g0] || !outs[g0 + 1] || dt == CPM_F64) return CPM_OK;
             bool pair = false;
-            const cpm_status r =
-                tree_pair_leaf(tree, dims, factors, R, g0, dt, w, outs[g0], outs[g0 + 1], stream, &pair);
+            const cpm_status r = tree_pair_leaf(tree, dims, factors, R, g0, dt, w, outs[g0], outs[g0 + 1], stream,
+                                                &pair, merge ? &sums : nullptr);
             done[g0] = done[g0 + 1] = pair;
             return r;
         };
@@ -1159,12 +1201,15 @@ cpm_status all_enqueue(const void *X, const int64_t *dims, int N, const void *co
         }
         if (want_right) {
             const bool one = tree_single(tree, N, N - 1);
-            s = tree_pass(tree, false, X, factors, R, dt, w, stream, one ? outs[N - 1] : nullptr);
+            s = tree_pass(tree, false, X, factors, R, dt, w, stream, one ? outs[N - 1] : nullptr,
+                          merge ? &sums : nullptr);
             if (s) return s;
             done[N - 1] = one;
             s = pair_of(tree.s);
             if (s) return s;
         }
+        s = sum_flush(sums, stream);
+        if (s) return s;
     }
     for (int n = 0; n < N; ++n) {
         if (!outs[n] || done[n]) continue;

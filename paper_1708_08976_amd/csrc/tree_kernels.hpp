@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_tree_leaf4(const float *__restrict
 //   M_b: each worker adds over its wave's a values in order; the four
 //     waves are added in order through LDS and written to slice blockIdx.y
 //     of PB [gridDim.y][B][R].
-// All sums in float64 in a fixed order; k_pair_reduce adds the slices.  A
+// All sums in float64 in a fixed order; k_sum_jobs adds the slices.  A
 // grid dimension of 1 makes the slice the result itself.  Needs R a
 // multiple of 4, R <= 4 * RC, 16-byte aligned T, factors and PA, and
 // (A * B + kPairTB) * R * 4 below 2^32 (buffer offsets).
@@ -350,22 +350,28 @@ __global__ __launch_bounds__(kThreads) void k_pair_leaf(const float *__restrict_
     }
 }
 
-// The slice sums of k_pair_leaf for both outputs in one launch: blocks
-// [0, blocks_a) take 64 consecutive entries of M_a, the rest of M_b.  The
+// Sums of partial slices for up to kSumJobs outputs in one launch (the
+// slices of k_pair_leaf, and a pass's split-K partials when the pass writes
+// a result): job j takes blocks [first[j], first[j + 1]), each 64
+// consecutive entries e of M_j = sum over q < S_j of P_j[q * n_j + e].  The
 // four waves of a block take interleaved slices and are added in wave
-// order, in float64.  S == 0 skips that output (its slice was the result).
-__global__ __launch_bounds__(kThreads) void k_pair_reduce(const float *__restrict__ PA, int64_t SA, int64_t A,
-                                                          float *__restrict__ MA, const float *__restrict__ PB,
-                                                          int64_t SB, int64_t B, float *__restrict__ MB, int R,
-                                                          int64_t blocks_a) {
+// order, in float64: the order of k_reduce's plain sums.
+constexpr int kSumJobs = 4;
+struct SumJobs {
+    const float *P[kSumJobs];
+    float *M[kSumJobs];
+    int64_t S[kSumJobs], n[kSumJobs];
+    int64_t first[kSumJobs + 1];
+    int count;
+};
+__global__ __launch_bounds__(kThreads) void k_sum_jobs(SumJobs J) {
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool is_a = (int64_t)blockIdx.x < blocks_a;
-    const float *P = is_a ? PA : PB;
-    const int64_t S = is_a ? SA : SB;
-    const int64_t total = (is_a ? A : B) * R;
-    float *M = is_a ? MA : MB;
-    const int64_t e = ((int64_t)blockIdx.x - (is_a ? 0 : blocks_a)) * 64 + lane;
+    int j = 0;
+    while (j + 1 < J.count && (int64_t)blockIdx.x >= J.first[j + 1]) ++j;
+    const float *P = J.P[j];
+    const int64_t S = J.S[j], total = J.n[j];
+    const int64_t e = ((int64_t)blockIdx.x - J.first[j]) * 64 + lane;
     double s = 0.0;
     if (e < total) {
 #pragma unroll 4
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_reduce(const float *__restric
     }
     red[wave][lane] = s;
     __syncthreads();
-    if (wave == 0 && e < total) M[e] = (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+    if (wave == 0 && e < total) J.M[j][e] = (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
 }  // namespace cpm
