@@ -133,10 +133,27 @@ constexpr size_t kTileBytes = 78 * 1024;   // LDS for the resident Khatri-Rao ti
 // Splits the outer blocks so the grid holds at most `groups` work-groups
 // (one round of resident work-groups): rounding the split count up instead
 // put a grid just past a round (516 for 512 slots) in two rounds of the
-// same length.
+// same length.  When that round would be less than 85% full (257 tiles for
+// 512 slots), the split count with the shortest estimated time is taken
+// instead: rounds x (blocks per work-group + 2 for its set-up), with at
+// most 1024 partial slices.  Grids of several rounds are left as they are:
+// their work-groups do not finish together, so a short last round costs
+// less than that estimate says (splitting further measured slower).
 void split_outer(Plan &p, int64_t groups) {
-    int64_t S = std::max<int64_t>(1, groups / (p.ntiles * p.nlc * p.ncb));
-    S = std::min(S, p.n_outer);
+    const int64_t T = p.ntiles * p.nlc * p.ncb;
+    int64_t S = std::min(std::max<int64_t>(1, groups / T), p.n_outer);
+    if (T * S < groups * 85 / 100) {
+        const int64_t smax = std::max(S, std::min(p.n_outer, (int64_t)1024 / p.nlc));
+        int64_t best = -1;
+        for (int64_t s = 1; s <= smax; ++s) {
+            const int64_t b = ceil_div(p.n_outer, s), s2 = ceil_div(p.n_outer, b);
+            const int64_t cost = ceil_div(T * s2, groups) * (b + 2);
+            if (best < 0 || cost < best) {
+                best = cost;
+                S = s2;
+            }
+        }
+    }
     p.bps = ceil_div(p.n_outer, S);
     p.S = ceil_div(p.n_outer, p.bps);
 }
