@@ -267,12 +267,19 @@ def test_mttkrp_all_three_way_reuse_matches_oracle(dims, ranks):
         announce("mttkrp_all 3-way", dims, R)
         assert uses_reuse(dims, R, _abi.CPM_F32), (dims, R)
         X, U = make_case(dims, R, seed=sum(dims) + R)
-        outs = _abi.mttkrp_all(X.cuda(), dims, [u.cuda() for u in U])
+        Xd, Ud = X.cuda(), [u.cuda() for u in U]
+        outs = _abi.mttkrp_all(Xd, dims, Ud)
         torch.cuda.synchronize()
         Xh, Uh = X.numpy().ravel(), [u.numpy() for u in U]
         for n in range(3):
             err = rel_err(outs[n].cpu().numpy(), O.mttkrp(Xh, dims, Uh, n))
             assert err <= TOL["f32"], (dims, R, n, err)
+        # mode 2 is the ordinary pass; its split-K sums, launched together
+        # with the pair leaf's slice sums, add in the same order as the
+        # single-mode call's reduction
+        single = _abi.mttkrp(Xd, dims, Ud, 2)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[2], single), (dims, R)
 
 
 def test_als_sweep_three_way_reuse_matches_oracle():
